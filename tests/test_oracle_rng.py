@@ -1,0 +1,94 @@
+"""Pins of the oracle's random numbers.
+
+The paper only says xi_n ~ N(0, 1) i.i.d. (Sec. 3.1). The oracle draws them with
+Philox4x32-10 and Box-Muller. Published known-answer vectors for Philox are not
+available offline, so the bit pattern itself is a convention shared with the GPU
+path (two independent implementations must agree bitwise); what the method needs -
+independent standard normals - is pinned here statistically.
+"""
+import numpy as np
+import pytest
+from scipy import stats
+
+import workloads as W
+
+
+def _words(orc, n, key=(42, 0)):
+    out = np.empty((n, 4), dtype=np.uint64)
+    for i in range(n):
+        out[i] = orc.philox([i, 0, 0, 0], list(key))
+    return out
+
+
+def test_philox_words_uniform_and_balanced(orc):
+    w = _words(orc, 20000)
+    # every output word: byte histogram uniform, every bit balanced
+    for col in range(4):
+        bytes_ = np.concatenate([(w[:, col] >> (8 * b)) & 0xFF for b in range(4)])
+        counts = np.bincount(bytes_.astype(np.int64), minlength=256)
+        assert stats.chisquare(counts).pvalue > 1e-4
+        bits = np.array([((w[:, col] >> b) & 1).mean() for b in range(32)])
+        assert np.all(np.abs(bits - 0.5) < 5 * 0.5 / np.sqrt(len(w)))
+
+
+def test_philox_avalanche(orc):
+    """Flipping one counter or key bit flips about half of the 128 output bits."""
+    rng = np.random.default_rng(0)
+    flips = []
+    for _ in range(300):
+        ctr = [int(x) for x in rng.integers(0, 2**32, 4)]
+        key = [int(x) for x in rng.integers(0, 2**32, 2)]
+        base = orc.philox(ctr, key)
+        j = int(rng.integers(0, 6))
+        b = int(rng.integers(0, 32))
+        c2, k2 = list(ctr), list(key)
+        if j < 4:
+            c2[j] ^= 1 << b
+        else:
+            k2[j - 4] ^= 1 << b
+        new = orc.philox(c2, k2)
+        flips.append(sum(bin(x ^ y).count("1") for x, y in zip(base, new)))
+    flips = np.array(flips)
+    assert abs(flips.mean() - 64.0) < 1.5
+    assert flips.min() > 30
+
+
+def test_normals_are_standard_and_independent(orc):
+    p = W.problem()
+    z = np.array([orc.normals(p, 1, i, m) for i in range(400) for m in range(50)])
+    a, b = z[:, 0], z[:, 1]
+    n = len(a)
+    for x in (a, b):
+        assert abs(x.mean()) < 5 / np.sqrt(n)
+        assert abs(x.var() - 1.0) < 5 * np.sqrt(2.0 / n)
+        assert abs(stats.skew(x)) < 5 * np.sqrt(6.0 / n)
+        assert abs(stats.kurtosis(x)) < 5 * np.sqrt(24.0 / n)
+        assert stats.kstest(x, "norm").pvalue > 1e-4
+    assert abs(np.corrcoef(a, b)[0, 1]) < 5 / np.sqrt(n)
+    # consecutive blocks of one sample are uncorrelated
+    aa = a.reshape(400, 50)
+    assert abs(np.corrcoef(aa[:, :-1].ravel(), aa[:, 1:].ravel())[0, 1]) < 5 / np.sqrt(n)
+    # the pair is rotation invariant: a^2 + b^2 ~ chi2(2)
+    assert stats.kstest(a * a + b * b, "chi2", args=(2,)).pvalue > 1e-4
+
+
+def test_streams_levels_and_seeds_are_distinct(orc):
+    base = W.problem()
+    ref = orc.normals(base, 3, 5, 7)
+    assert orc.normals(dict(base, seed=43), 3, 5, 7) != ref
+    assert orc.normals(dict(base, stream_id=1), 3, 5, 7) != ref
+    assert orc.normals(base, 4, 5, 7) != ref
+    assert orc.normals(base, 3, 5 + (1 << 32), 7) != ref
+    assert orc.normals(base, 3, 5, 8) != ref
+    assert orc.normals(base, 3, 5, 7) == ref
+
+
+def test_uniform_map_is_open_interval(orc):
+    """Extreme words map strictly inside (0, 1), so log never sees 0: the largest
+    normal is finite. Built from the word values 0 and 2^32-1 through the public
+    Box-Muller draw by searching counters is impractical, so check the tail bound:
+    with 52-bit uniforms |xi| <= sqrt(-2 ln 2^-53) = 8.57."""
+    p = W.problem()
+    z = np.array([orc.normals(p, 0, i, 0) for i in range(20000)])
+    assert np.all(np.isfinite(z))
+    assert np.abs(z).max() < np.sqrt(-2 * np.log(2.0**-53))
