@@ -1,0 +1,256 @@
+/*
+ * ldmlmc.h -- C ABI of the MI355X (gfx950) multilevel Monte Carlo library for
+ * Lagrangian atmospheric dispersion.
+ *
+ * Method: G. Katsiolides, E. H. Mueller, R. Scheichl, T. Shardlow, M. B. Giles,
+ * D. J. Thomson, "Multilevel Monte Carlo and improved timestepping methods in
+ * atmospheric dispersion modelling", arXiv:1612.07717. Section and equation numbers
+ * below are the paper's.
+ *
+ * The library estimates E[phi(X_T)] for the one-dimensional vertical Langevin model of
+ * Sec. 2 (Eq. 4, profiles Eq. 5, cut-off Eq. 7, elastic reflection at 0 and H, Eq. 6)
+ * with the multilevel Monte Carlo estimator of Sec. 3.3 (Eqs. 14-17). Each level
+ * couples a fine path of M_l = M_0 2^l steps with a coarse path of M_l / 2 steps
+ * driven by the combined fine increments (Eqs. 18-19), with the reflection sign
+ * factors of Sec. 4 (Eqs. 31-32). Integrators: symplectic Euler (Eq. 8), geometric
+ * Langevin (Eq. 9) and BAOAB (Eq. 10).
+ *
+ * Conventions
+ *  - SI units throughout (metres, seconds, m/s).
+ *  - Every function returns an int status: LD_OK (0), a positive warning with a valid
+ *    result, or a negative error. Nothing throws across the ABI; nothing exits.
+ *  - Pointers named d_* are DEVICE pointers (hipMalloc or a torch CUDA tensor's
+ *    data_ptr on the current device); all others are host pointers. The caller owns
+ *    every buffer; the library keeps no pointer after a call returns.
+ *  - hip_stream is a hipStream_t (NULL = the default stream). Level-sum calls only
+ *    enqueue work on it and return; mlmc_estimate blocks until done.
+ *  - Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by `seed`, counter =
+ *    (block, sample_lo, sample_hi, level | stream_id << 8), Box-Muller normals. A
+ *    sample's result depends only on (problem, integrator, precision, level, sample
+ *    index), never on launch shape or batching.
+ *  - Level sums are FP64 compensated (Neumaier) sums in both precisions; the
+ *    precision selects the arithmetic of the particle paths only.
+ */
+#ifndef LDMLMC_H
+#define LDMLMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LDMLMC_ABI_VERSION 1
+#define LD_MAX_LEVELS 32
+
+/* ---- status codes ------------------------------------------------------------- */
+#define LD_OK 0
+#define LD_WARN_NOT_CONVERGED 1  /* mlmc_estimate stopped at L_max or max_iter; result filled */
+#define LD_EINVAL (-1)           /* invalid argument (bad parameter, null pointer, size)    */
+#define LD_EUNSTABLE (-2)        /* symplectic Euler with lambda_max * h >= 2 (Sec. 3.1)     */
+#define LD_ENOMEM (-3)           /* workspace smaller than the *_workspace() size           */
+#define LD_EDEVICE (-4)          /* HIP runtime error; ld_last_error() has the message       */
+#define LD_ENONFINITE (-5)       /* some samples were non-finite (excluded from the sums)    */
+#define LD_ENODEVICE (-6)        /* no usable gfx950 device                                 */
+
+typedef enum { LD_SE = 0, LD_GL = 1, LD_BAOAB = 2 } ld_integrator;   /* Eqs. 8, 9, 10 */
+typedef enum { LD_FP64 = 0, LD_FP32 = 1 } ld_precision;              /* path arithmetic */
+
+enum { LD_PROFILE_HOMOGENEOUS = 0, LD_PROFILE_NEUTRAL_BL = 1 };
+enum { LD_RELEASE_FIXED_W = 0, LD_RELEASE_GAUSSIAN_W = 1, LD_RELEASE_WELL_MIXED = 2 };
+enum {
+    LD_QOI_MEAN_Z = 0,      /* phi = X_T (Sec. 2)                                         */
+    LD_QOI_P_ABOVE = 1,     /* phi = 1(X_T > a); r > 0: 1 - g_r((X_T - a)/delta) (Sec. 5)  */
+    LD_QOI_P_BOX = 2,       /* phi = 1_(a,b](X_T) (Eq. 34); r > 0: Eq. 37                   */
+    LD_QOI_VELOCITY = 3,    /* phi = U_T                                                  */
+    LD_QOI_VELOCITY_SQ = 4  /* phi = U_T^2                                                */
+};
+
+/* Turbulence profile. NEUTRAL_BL: sigma_U = kappa_sigma u_* (1 - X/H)^(3/4),
+   tau = kappa_tau X / sigma_U (Eq. 5), frozen below eps_reg and above H - eps_reg
+   (Eq. 7). HOMOGENEOUS: constant sigma_u and tau. Valid: H > 0; NEUTRAL_BL needs
+   kappa_sigma, kappa_tau, u_star > 0 and 0 < eps_reg < H/2; HOMOGENEOUS needs
+   sigma_u > 0 and tau > 0. */
+typedef struct {
+    int32_t kind;
+    int32_t reserved;
+    double H;
+    double sigma_u, tau;
+    double kappa_sigma, kappa_tau, u_star, eps_reg;
+} ld_profile;
+
+/* Quantity of interest. r = 0 selects the raw indicator; 1 <= r <= 8 the smoothed one
+   with polynomial p_r of Eq. (35) and width delta > 0 (Sec. 5). */
+typedef struct {
+    int32_t kind;
+    int32_t r;
+    double a, b, delta;
+} ld_qoi;
+
+/* Initial condition, shared by the fine and the coarse path. FIXED_W: X_0 = z0,
+   U_0 = w0. GAUSSIAN_W: X_0 = z0, U_0 ~ N(0, sigma_U(z0)^2). WELL_MIXED: X_0 ~ U(0, H),
+   U_0 ~ N(0, sigma_U(X_0)^2) (the invariant law of Sec. 2). 0 <= z0 <= H. */
+typedef struct {
+    int32_t kind;
+    int32_t reserved;
+    double z0, w0;
+} ld_release;
+
+/* One estimation problem. T > 0, M0 >= 1, stream_id < 2^24. */
+typedef struct {
+    ld_profile profile;
+    ld_release release;
+    ld_qoi qoi;
+    double T;
+    int32_t M0;
+    uint32_t stream_id;
+    uint64_t seed;
+} ld_problem;
+
+/* Compensated sums over the finite samples of one level: index 0 Y_l, 1 Y_l^2,
+   2 P_l, 3 P_l^2 (Y_l = P_l - P_{l-1}, Eq. 16; Y_0 = P_0). value_k = s[k] + c[k].
+   Samples with a non-finite result are counted in n_nonfinite and excluded. */
+typedef struct {
+    double s[4];
+    double c[4];
+    uint64_t n;
+    uint64_t n_nonfinite;
+} ld_level_sums;
+
+typedef struct {
+    int32_t level;
+    int32_t reserved;
+    uint64_t sample_begin;
+    uint64_t n_samples;
+} ld_level_range;
+
+/* ---- level sums ----------------------------------------------------------------- */
+
+/* Bytes of device workspace mlmc_level_sums needs for n_samples samples. */
+size_t mlmc_level_sums_workspace(uint64_t n_samples);
+
+/* Y_l and P_l sums of samples [sample_begin, sample_begin + n_samples) of `level`
+   (0 <= level < LD_MAX_LEVELS, M0 * 2^level <= 2^31), Sec. 3.3, Eq. (16).
+   d_out: one ld_level_sums in device memory, overwritten. d_workspace: at least
+   mlmc_level_sums_workspace(n_samples) bytes of device memory, contents undefined on
+   return. n_samples = 0 writes zero sums. Returns LD_EUNSTABLE for symplectic Euler
+   when lambda_max * h >= 2 for a step the level uses (Sec. 3.1). Asynchronous. */
+int mlmc_level_sums(const ld_problem* problem, ld_integrator integrator,
+                    ld_precision precision, int32_t level, uint64_t sample_begin,
+                    uint64_t n_samples, ld_level_sums* d_out, void* d_workspace,
+                    size_t workspace_bytes, void* hip_stream);
+
+/* Several (level, sample range) pairs of one problem in one launch; the most expensive
+   levels are dispatched first. d_out: n_ranges ld_level_sums in device memory, in the
+   order of `ranges`. 1 <= n_ranges <= LD_MAX_LEVELS. */
+size_t mlmc_level_sums_batch_workspace(const ld_level_range* ranges, int32_t n_ranges);
+int mlmc_level_sums_batch(const ld_problem* problem, ld_integrator integrator,
+                          ld_precision precision, const ld_level_range* ranges,
+                          int32_t n_ranges, ld_level_sums* d_out, void* d_workspace,
+                          size_t workspace_bytes, void* hip_stream);
+
+/* Per-sample results of the same kernels (a checking hook): d_pf_pc[2k] = P_l and
+   d_pf_pc[2k+1] = P_{l-1} (0 on level 0) of sample sample_begin + k, as FP64.
+   d_pf_pc holds 2 * n_samples doubles; d_workspace as for mlmc_level_sums. */
+int mlmc_level_samples(const ld_problem* problem, ld_integrator integrator,
+                       ld_precision precision, int32_t level, uint64_t sample_begin,
+                       uint64_t n_samples, double* d_pf_pc, void* d_workspace,
+                       size_t workspace_bytes, void* hip_stream);
+
+/* ---- the MLMC driver -------------------------------------------------------------- */
+
+/* One decision of the adaptive MLMC algorithm (host only, no device use). The MSE of
+   Eq. (17) is split evenly between bias and variance (Sec. 3.2, Sec. 6); with the
+   cost per sample C_l = M_l (condition (iv) of the theorem in Sec. 3.3) the optimal
+   N_l = ceil(2 eps^-2 sqrt(V_l / C_l) sum_k sqrt(V_k C_k)). Levels needing more than 1%
+   more samples get them; otherwise the bias is estimated as
+   max(|Yhat_L|, |Yhat_{L-1}| 2^-alpha) / (2^alpha - 1) and a level is added (with
+   V_{L+1} = V_L / 4, condition (iii)) while it exceeds eps / sqrt(2). alpha <= 0 fits
+   the weak order to log2 |Yhat_l|, clamped to [0.5, 2]; the paper's integrators are
+   first order (Sec. 3.1), the default alpha = 1. */
+typedef struct {
+    int32_t L;                          /* current finest level */
+    int32_t M0;
+    uint64_t n[LD_MAX_LEVELS];          /* finite samples so far per level */
+    double sum1[LD_MAX_LEVELS];         /* sum of Y_l */
+    double sum2[LD_MAX_LEVELS];         /* sum of Y_l^2 */
+    double eps;                         /* RMSE target, absolute or relative */
+    double alpha;
+    int32_t eps_is_relative;            /* eps_abs = eps * |sum_l Yhat_l| */
+    int32_t L_max;
+    int32_t fixed_L;                    /* >= 0: never add levels */
+    int32_t fixed_N;                    /* nonzero: no adaptation at all */
+    uint64_t N_init;                    /* minimum first batch of a new level */
+} ld_plan_in;
+
+typedef struct {
+    int32_t status;                     /* 0 more samples, 1 converged, 2 stopped at L_max */
+    int32_t L;                          /* finest level after this decision */
+    uint64_t dn[LD_MAX_LEVELS];         /* extra samples per level */
+    double Yhat[LD_MAX_LEVELS], V[LD_MAX_LEVELS];
+    double estimate, eps_abs, alpha, bias_est, stat_var;
+} ld_plan_out;
+
+int mlmc_plan(const ld_plan_in* in, ld_plan_out* out);
+
+typedef struct {
+    ld_release release;
+    double T;
+    int32_t M0;
+    int32_t L_min;           /* first levels 0..L_min (default 2) */
+    int32_t L_max;           /* default 20 */
+    int32_t fixed_L;         /* >= 0: levels 0..fixed_L, no bias test (default -1) */
+    int32_t fixed_N;         /* nonzero: N_init samples on every level, one batch */
+    int32_t eps_is_relative;
+    uint64_t N_init;         /* first batch per level (default 10000) */
+    double alpha;            /* weak order for the bias test (default 1) */
+    ld_precision precision;  /* path arithmetic (default LD_FP64) */
+    uint32_t stream_id;
+    uint64_t seed;
+    int32_t max_iter;        /* default 100 */
+    int32_t reserved;
+    void* d_workspace;       /* NULL: allocated and freed inside the call */
+    size_t workspace_bytes;
+    void* hip_stream;
+} ld_estimate_opts;
+
+typedef struct {
+    double estimate;         /* sum_l Yhat_l (Eq. 15) */
+    double eps_abs;
+    double bias_est;
+    double stat_var;         /* sum_l V_l / N_l */
+    double rmse_est;         /* sqrt(bias_est^2 + stat_var) */
+    double alpha;
+    int32_t L, iterations, status, reserved;
+    uint64_t N[LD_MAX_LEVELS];
+    uint64_t n_nonfinite;
+    double Yhat[LD_MAX_LEVELS], V[LD_MAX_LEVELS];
+    double fine_steps;       /* sum_l N_l M_l: coupled particle-steps */
+    double integrator_steps; /* sum_l N_l (M_l + M_l/2) (M_0 on level 0) */
+    double wall_seconds;
+    double device_seconds;   /* time inside the level-sum kernels (HIP events) */
+    int32_t launches;
+    int32_t reserved2;
+} ld_estimate_result;
+
+void mlmc_estimate_default_opts(ld_estimate_opts* opts);
+/* Bytes of workspace mlmc_estimate may need when d_workspace is given. */
+size_t mlmc_estimate_workspace(void);
+
+/* Adaptive MLMC estimate of E[phi(X_T)] to RMSE eps (Sec. 3.3, Sec. 6). Blocks until
+   done. opts NULL = defaults (which release at z0 = 0 with w0 = 0: pass opts). out is
+   filled also on LD_WARN_NOT_CONVERGED and LD_ENONFINITE. */
+int mlmc_estimate(double eps, const ld_qoi* qoi, ld_integrator integrator,
+                  const ld_profile* profile, const ld_estimate_opts* opts,
+                  ld_estimate_result* out);
+
+/* ---- errors --------------------------------------------------------------------- */
+const char* ld_strerror(int status);
+/* Message of the last error on the calling thread ("" if none). */
+const char* ld_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

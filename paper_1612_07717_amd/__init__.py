@@ -1,0 +1,333 @@
+"""Python binding of libldmlmc (include/ldmlmc.h): argument marshalling only.
+
+Every step of the method runs in the HIP library; this module converts workload dicts
+(see workloads.py) to the C structs, takes device memory and the current stream from
+PyTorch, and converts results back. If the library has not been built the import
+still works but every call raises; there is no other code path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libldmlmc.so")
+MAX_LEVELS = 32
+
+LD_OK, LD_WARN_NOT_CONVERGED = 0, 1
+LD_EINVAL, LD_EUNSTABLE, LD_ENOMEM, LD_EDEVICE, LD_ENONFINITE, LD_ENODEVICE = -1, -2, -3, -4, -5, -6
+
+INTEGRATORS = {"SE": 0, "GL": 1, "BAOAB": 2}
+PRECISIONS = {"fp64": 0, "fp32": 1}
+PROFILES = {"homogeneous": 0, "neutral": 1}
+RELEASES = {"fixed": 0, "gaussian": 1, "well_mixed": 2}
+QOIS = {"mean_z": 0, "p_above": 1, "p_box": 2, "velocity": 3, "velocity_sq": 4}
+
+EXPORTED = ["mlmc_level_sums_workspace", "mlmc_level_sums", "mlmc_level_sums_batch_workspace",
+            "mlmc_level_sums_batch", "mlmc_level_samples", "mlmc_plan",
+            "mlmc_estimate_default_opts", "mlmc_estimate_workspace", "mlmc_estimate",
+            "ld_strerror", "ld_last_error"]
+
+
+class LdError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"ldmlmc status {status}: {message}")
+        self.status = status
+
+
+class Profile(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("H", C.c_double),
+                ("sigma_u", C.c_double), ("tau", C.c_double), ("kappa_sigma", C.c_double),
+                ("kappa_tau", C.c_double), ("u_star", C.c_double), ("eps_reg", C.c_double)]
+
+
+class Qoi(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("r", C.c_int32), ("a", C.c_double), ("b", C.c_double),
+                ("delta", C.c_double)]
+
+
+class Release(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("reserved", C.c_int32), ("z0", C.c_double),
+                ("w0", C.c_double)]
+
+
+class Problem(C.Structure):
+    _fields_ = [("profile", Profile), ("release", Release), ("qoi", Qoi), ("T", C.c_double),
+                ("M0", C.c_int32), ("stream_id", C.c_uint32), ("seed", C.c_uint64)]
+
+
+class LevelSums(C.Structure):
+    _fields_ = [("s", C.c_double * 4), ("c", C.c_double * 4), ("n", C.c_uint64),
+                ("n_nonfinite", C.c_uint64)]
+
+
+class LevelRange(C.Structure):
+    _fields_ = [("level", C.c_int32), ("reserved", C.c_int32), ("sample_begin", C.c_uint64),
+                ("n_samples", C.c_uint64)]
+
+
+class PlanIn(C.Structure):
+    _fields_ = [("L", C.c_int32), ("M0", C.c_int32), ("n", C.c_uint64 * MAX_LEVELS),
+                ("sum1", C.c_double * MAX_LEVELS), ("sum2", C.c_double * MAX_LEVELS),
+                ("eps", C.c_double), ("alpha", C.c_double), ("eps_is_relative", C.c_int32),
+                ("L_max", C.c_int32), ("fixed_L", C.c_int32), ("fixed_N", C.c_int32),
+                ("N_init", C.c_uint64)]
+
+
+class PlanOut(C.Structure):
+    _fields_ = [("status", C.c_int32), ("L", C.c_int32), ("dn", C.c_uint64 * MAX_LEVELS),
+                ("Yhat", C.c_double * MAX_LEVELS), ("V", C.c_double * MAX_LEVELS),
+                ("estimate", C.c_double), ("eps_abs", C.c_double), ("alpha", C.c_double),
+                ("bias_est", C.c_double), ("stat_var", C.c_double)]
+
+
+class EstimateOpts(C.Structure):
+    _fields_ = [("release", Release), ("T", C.c_double), ("M0", C.c_int32),
+                ("L_min", C.c_int32), ("L_max", C.c_int32), ("fixed_L", C.c_int32),
+                ("fixed_N", C.c_int32), ("eps_is_relative", C.c_int32), ("N_init", C.c_uint64),
+                ("alpha", C.c_double), ("precision", C.c_int32), ("stream_id", C.c_uint32),
+                ("seed", C.c_uint64), ("max_iter", C.c_int32), ("reserved", C.c_int32),
+                ("d_workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+                ("hip_stream", C.c_void_p)]
+
+
+class EstimateResult(C.Structure):
+    _fields_ = [("estimate", C.c_double), ("eps_abs", C.c_double), ("bias_est", C.c_double),
+                ("stat_var", C.c_double), ("rmse_est", C.c_double), ("alpha", C.c_double),
+                ("L", C.c_int32), ("iterations", C.c_int32), ("status", C.c_int32),
+                ("reserved", C.c_int32), ("N", C.c_uint64 * MAX_LEVELS),
+                ("n_nonfinite", C.c_uint64), ("Yhat", C.c_double * MAX_LEVELS),
+                ("V", C.c_double * MAX_LEVELS), ("fine_steps", C.c_double),
+                ("integrator_steps", C.c_double), ("wall_seconds", C.c_double),
+                ("device_seconds", C.c_double), ("launches", C.c_int32),
+                ("reserved2", C.c_int32)]
+
+
+_lib = None
+
+
+def load():
+    """Load libldmlmc.so. Raises if it has not been built: there is no fallback."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_1612_07717_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    P, V = C.POINTER, C.c_void_p
+    lib.mlmc_level_sums_workspace.argtypes = [C.c_uint64]
+    lib.mlmc_level_sums_workspace.restype = C.c_size_t
+    lib.mlmc_level_sums.argtypes = [P(Problem), C.c_int, C.c_int, C.c_int32, C.c_uint64,
+                                    C.c_uint64, V, V, C.c_size_t, V]
+    lib.mlmc_level_sums_batch_workspace.argtypes = [P(LevelRange), C.c_int32]
+    lib.mlmc_level_sums_batch_workspace.restype = C.c_size_t
+    lib.mlmc_level_sums_batch.argtypes = [P(Problem), C.c_int, C.c_int, P(LevelRange),
+                                          C.c_int32, V, V, C.c_size_t, V]
+    lib.mlmc_level_samples.argtypes = [P(Problem), C.c_int, C.c_int, C.c_int32, C.c_uint64,
+                                       C.c_uint64, V, V, C.c_size_t, V]
+    lib.mlmc_plan.argtypes = [P(PlanIn), P(PlanOut)]
+    lib.mlmc_estimate_default_opts.argtypes = [P(EstimateOpts)]
+    lib.mlmc_estimate_default_opts.restype = None
+    lib.mlmc_estimate_workspace.restype = C.c_size_t
+    lib.mlmc_estimate.argtypes = [C.c_double, P(Qoi), C.c_int, P(Profile), P(EstimateOpts),
+                                  P(EstimateResult)]
+    lib.ld_strerror.argtypes = [C.c_int]
+    lib.ld_strerror.restype = C.c_char_p
+    lib.ld_last_error.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, ok=(LD_OK,)) -> int:
+    if rc not in ok:
+        lib = load()
+        raise LdError(rc, f"{lib.ld_strerror(rc).decode()}: {lib.ld_last_error().decode()}")
+    return rc
+
+
+# ----------------------------------------------------------------------------- structs
+def make_profile(cfg: dict) -> Profile:
+    return Profile(kind=PROFILES[cfg["profile"]], H=cfg["H"], sigma_u=cfg["sigma_u"],
+                   tau=cfg["tau"], kappa_sigma=cfg["kappa_sigma"], kappa_tau=cfg["kappa_tau"],
+                   u_star=cfg["u_star"], eps_reg=cfg["eps_reg"])
+
+
+def make_qoi(cfg: dict) -> Qoi:
+    return Qoi(kind=QOIS[cfg["qoi"]], r=int(cfg["r"]), a=cfg["qa"], b=cfg["qb"],
+               delta=cfg["delta"])
+
+
+def make_release(cfg: dict) -> Release:
+    return Release(kind=RELEASES[cfg["release"]], z0=cfg["z0"], w0=cfg["w0"])
+
+
+def make_problem(cfg: dict) -> Problem:
+    if cfg.get("coupling", "reflected") != "reflected":
+        raise ValueError("the library implements the reflection-aware coupling only")
+    return Problem(profile=make_profile(cfg), release=make_release(cfg), qoi=make_qoi(cfg),
+                   T=cfg["T"], M0=int(cfg["M0"]), stream_id=int(cfg["stream_id"]),
+                   seed=int(cfg["seed"]))
+
+
+def sums_to_dict(s: LevelSums) -> dict:
+    v = [s.s[k] + s.c[k] for k in range(4)]
+    return {"sum_y": v[0], "sum_y2": v[1], "sum_pf": v[2], "sum_pf2": v[3],
+            "s": list(s.s), "c": list(s.c), "n": int(s.n), "n_nonfinite": int(s.n_nonfinite)}
+
+
+# ------------------------------------------------------------------------- device calls
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU visible to PyTorch")
+    return torch
+
+
+def _stream_handle(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def level_sums_workspace(n: int) -> int:
+    return int(load().mlmc_level_sums_workspace(int(n)))
+
+
+def level_sums_async(cfg, level, begin, n, out, workspace, precision="fp64", stream=None):
+    """Enqueue mlmc_level_sums into torch tensors: `out` >= 80 bytes, `workspace` >=
+    level_sums_workspace(n) bytes (both CUDA tensors). Does not synchronise."""
+    lib = load()
+    p = make_problem(cfg)
+    _check(lib.mlmc_level_sums(C.byref(p), INTEGRATORS[cfg["integrator"]], PRECISIONS[precision],
+                               int(level), int(begin), int(n), C.c_void_p(out.data_ptr()),
+                               C.c_void_p(workspace.data_ptr()),
+                               workspace.numel() * workspace.element_size(), _stream_handle(stream)))
+
+
+def _sums_from_tensor(t) -> dict:
+    raw = t.detach().cpu().contiguous().view(-1).numpy().view(np.uint8)[: C.sizeof(LevelSums)]
+    return sums_to_dict(LevelSums.from_buffer_copy(raw.tobytes()))
+
+
+def level_sums(cfg, level, begin, n, precision="fp64", stream=None) -> dict:
+    torch = _torch()
+    out = torch.zeros(C.sizeof(LevelSums), dtype=torch.uint8, device="cuda")
+    ws = torch.empty(max(level_sums_workspace(n), 1), dtype=torch.uint8, device="cuda")
+    level_sums_async(cfg, level, begin, n, out, ws, precision, stream)
+    torch.cuda.synchronize()
+    return _sums_from_tensor(out)
+
+
+def level_sums_batch(cfg, ranges, precision="fp64", stream=None) -> list:
+    """ranges: list of (level, begin, n). Returns one sums dict per range."""
+    torch = _torch()
+    lib = load()
+    arr = (LevelRange * len(ranges))(*[LevelRange(level=l, sample_begin=b, n_samples=n)
+                                       for l, b, n in ranges])
+    need = int(lib.mlmc_level_sums_batch_workspace(arr, len(ranges)))
+    ws = torch.empty(max(need, 1), dtype=torch.uint8, device="cuda")
+    out = torch.zeros(C.sizeof(LevelSums) * len(ranges), dtype=torch.uint8, device="cuda")
+    p = make_problem(cfg)
+    _check(lib.mlmc_level_sums_batch(C.byref(p), INTEGRATORS[cfg["integrator"]],
+                                     PRECISIONS[precision], arr, len(ranges),
+                                     C.c_void_p(out.data_ptr()), C.c_void_p(ws.data_ptr()),
+                                     ws.numel(), _stream_handle(stream)))
+    torch.cuda.synchronize()
+    raw = out.cpu().numpy().tobytes()
+    size = C.sizeof(LevelSums)
+    return [sums_to_dict(LevelSums.from_buffer_copy(raw[i * size:(i + 1) * size]))
+            for i in range(len(ranges))]
+
+
+def level_samples(cfg, level, begin, n, precision="fp64", stream=None) -> np.ndarray:
+    """Per-sample (P_l, P_{l-1}) in FP64, shape (n, 2)."""
+    torch = _torch()
+    lib = load()
+    out = torch.empty((max(n, 1), 2), dtype=torch.float64, device="cuda")
+    ws = torch.empty(max(level_sums_workspace(n), 1), dtype=torch.uint8, device="cuda")
+    p = make_problem(cfg)
+    _check(lib.mlmc_level_samples(C.byref(p), INTEGRATORS[cfg["integrator"]],
+                                  PRECISIONS[precision], int(level), int(begin), int(n),
+                                  C.c_void_p(out.data_ptr()), C.c_void_p(ws.data_ptr()),
+                                  ws.numel(), _stream_handle(stream)))
+    torch.cuda.synchronize()
+    return out[:n].cpu().numpy()
+
+
+def estimate_opts(cfg, *, precision="fp64", L_min=2, L_max=20, fixed_L=-1, fixed_N=False,
+                  N_init=10000, eps_is_relative=False, alpha=1.0, max_iter=100,
+                  workspace=None, stream=None) -> EstimateOpts:
+    o = EstimateOpts()
+    load().mlmc_estimate_default_opts(C.byref(o))
+    o.release = make_release(cfg)
+    o.T = cfg["T"]
+    o.M0 = int(cfg["M0"])
+    o.L_min, o.L_max, o.fixed_L, o.fixed_N = L_min, L_max, fixed_L, int(bool(fixed_N))
+    o.eps_is_relative = int(bool(eps_is_relative))
+    o.N_init = int(N_init)
+    o.alpha = float(alpha)
+    o.precision = PRECISIONS[precision]
+    o.stream_id = int(cfg["stream_id"])
+    o.seed = int(cfg["seed"])
+    o.max_iter = int(max_iter)
+    if workspace is not None:
+        o.d_workspace = workspace.data_ptr()
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
+    if stream is not None or workspace is not None:
+        o.hip_stream = _stream_handle(stream).value
+    return o
+
+
+def estimate_workspace_bytes() -> int:
+    return int(load().mlmc_estimate_workspace())
+
+
+def estimate(eps, cfg, **kw) -> dict:
+    """mlmc_estimate(eps, qoi, integrator, profile) with options from cfg and kw."""
+    lib = load()
+    o = estimate_opts(cfg, **kw)
+    r = EstimateResult()
+    q, prof = make_qoi(cfg), make_profile(cfg)
+    rc = lib.mlmc_estimate(float(eps), C.byref(q), INTEGRATORS[cfg["integrator"]],
+                           C.byref(prof), C.byref(o), C.byref(r))
+    _check(rc, ok=(LD_OK, LD_WARN_NOT_CONVERGED, LD_ENONFINITE))
+    L = r.L
+    return {"rc": rc, "estimate": r.estimate, "eps_abs": r.eps_abs, "bias_est": r.bias_est,
+            "stat_var": r.stat_var, "rmse_est": r.rmse_est, "alpha": r.alpha, "L": L,
+            "iterations": r.iterations, "status": r.status,
+            "N": [int(r.N[l]) for l in range(L + 1)], "n_nonfinite": int(r.n_nonfinite),
+            "Yhat": list(r.Yhat[: L + 1]), "V": list(r.V[: L + 1]),
+            "fine_steps": r.fine_steps, "integrator_steps": r.integrator_steps,
+            "wall_seconds": r.wall_seconds, "device_seconds": r.device_seconds,
+            "launches": r.launches}
+
+
+# --------------------------------------------------------------------------- host only
+def plan(d: dict) -> dict:
+    """mlmc_plan: one decision of the adaptive algorithm (host only, no GPU)."""
+    pin = PlanIn()
+    pin.L = d["L"]
+    pin.M0 = d["M0"]
+    for l, v in enumerate(d["n"]):
+        pin.n[l] = int(v)
+    for l, v in enumerate(d["sum1"]):
+        pin.sum1[l] = float(v)
+    for l, v in enumerate(d["sum2"]):
+        pin.sum2[l] = float(v)
+    pin.eps = d["eps"]
+    pin.alpha = d.get("alpha", 1.0)
+    pin.eps_is_relative = int(d.get("eps_is_relative", 0))
+    pin.L_max = d.get("L_max", 20)
+    pin.fixed_L = d.get("fixed_L", -1)
+    pin.fixed_N = int(d.get("fixed_N", 0))
+    pin.N_init = d.get("N_init", 10000)
+    out = PlanOut()
+    _check(load().mlmc_plan(C.byref(pin), C.byref(out)))
+    Lp = out.L
+    return {"status": out.status, "L": Lp, "dn": [int(out.dn[l]) for l in range(Lp + 1)],
+            "Yhat": list(out.Yhat[: d["L"] + 1]), "V": list(out.V[: d["L"] + 1]),
+            "estimate": out.estimate, "eps_abs": out.eps_abs, "alpha": out.alpha,
+            "bias_est": out.bias_est, "stat_var": out.stat_var}

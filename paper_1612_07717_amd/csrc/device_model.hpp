@@ -1,0 +1,328 @@
+// device_model.hpp -- one coupled MLMC sample per lane, state in registers (gfx950).
+//
+// Model (Sec. 2): dU = -lambda(X) U dt - dV/dX(X, U) dt + sigma(X) dW, dX = U dt
+// (Eq. 4) with lambda = 1/tau, sigma^2 = 2 sigma_U^2 / tau and the well-mixed drift
+// -dV/dX = (1/2)(1 + U^2/sigma_U^2) d(sigma_U^2)/dX (Eq. 3). For the neutral layer
+// (Eq. 5, cut off by Eq. 7) this drift is -a(X) - b(X) U^2 with
+//     a = (3/4) (kappa_sigma u_*)^2 sqrt(1 - X/H) / H,   b = (3/4) / (H - X)
+// inside [eps_reg, H - eps_reg] and 0 in the cut-off layers, where sigma_U is frozen.
+//
+// Integrators: symplectic Euler (Eq. 8), geometric Langevin OBA (Eq. 9), BAOAB
+// (Eq. 10). The O-step noise amplitude sigma sqrt((1 - e^{-2 lambda h}) / (2 lambda))
+// equals sigma_U sqrt(1 - w^2) with w = e^{-lambda h}; both w and 1 - w^2 come from one
+// e1 = expm1(-lambda h): w = 1 + e1, 1 - w^2 = -e1 (2 + e1), free of cancellation.
+//
+// Reflection (Eq. 6, Sec. 4): after every position update the position is folded back
+// into [0, H] (X -> -X or 2H - X), the velocity flips and the path's reflection sign S
+// flips. The noise entering a path is multiplied by the S in force at that moment:
+// the fine path's extended noise is S_f xi (Eq. 30), the coarse path's physical noise
+// is S_c times the combined extended noise (Eqs. 31, 32). S is kept as a sign-bit
+// mask, so applying it is one XOR.
+//
+// Coupling (Sec. 3.3): the coarse step 2h uses (xi~_2m + xi~_2m+1)/sqrt(2) for SE
+// (Eq. 18) and (w xi~_2m + xi~_2m+1)/sqrt(w^2 + 1) for GL and BAOAB (Eq. 19), w being
+// e^{-lambda h} of the first fine O-step of the pair.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_rng.hpp"
+#include "ld_internal.hpp"
+
+namespace ldm {
+
+constexpr uint32_t kSignBit = 0x80000000u;
+
+template <typename R>
+struct Math;
+
+template <>
+struct Math<float> {
+    static __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+    static __device__ __forceinline__ float flip(float v, uint32_t mask) {
+        return __uint_as_float(__float_as_uint(v) ^ mask);
+    }
+    // expm1 by argument reduction x = k ln2 + r, |r| <= ln2/2 (Cody & Waite's two-part
+    // ln2), the Taylor series of expm1(r) to degree 7 (truncation < 2e-8 relative), and
+    // expm1(x) = 2^k expm1(r) + (2^k - 1), which has no cancellation for k != 0.
+    static __device__ __forceinline__ float expm1_(float x) {
+        const float k = __builtin_rintf(x * 1.4426950408889634f);
+        float r = __builtin_fmaf(-k, 0.693145751953125f, x);
+        r = __builtin_fmaf(-k, 1.428606820309417e-06f, r);
+        float p = 1.0f / 5040.0f;
+        p = __builtin_fmaf(p, r, 1.0f / 720.0f);
+        p = __builtin_fmaf(p, r, 1.0f / 120.0f);
+        p = __builtin_fmaf(p, r, 1.0f / 24.0f);
+        p = __builtin_fmaf(p, r, 1.0f / 6.0f);
+        p = __builtin_fmaf(p, r, 0.5f);
+        p = __builtin_fmaf(p, r, 1.0f);
+        p = p * r;
+        const int ki = (int)k;
+        const float two_k = __builtin_amdgcn_ldexpf(1.0f, ki);
+        return __builtin_fmaf(two_k, p, two_k - 1.0f);
+    }
+};
+
+template <>
+struct Math<double> {
+    static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / sqrt(x); }
+    static __device__ __forceinline__ double flip(double v, uint32_t mask) {
+        return __hiloint2double(__double2hiint(v) ^ (int)mask, __double2loint(v));
+    }
+    static __device__ __forceinline__ double expm1_(double x) { return expm1(x); }
+};
+
+// Per-(problem, level) constants in the path precision.
+template <typename R>
+struct Consts {
+    R H, invH, eps, Hme;        // domain and cut-off heights
+    R ks;                       // kappa_sigma u_*
+    R acoef;                    // (3/4) (kappa_sigma u_*)^2 / H
+    R inv_kt;                   // 1 / kappa_tau
+    R su_h, lam_h;              // homogeneous sigma_U and lambda
+};
+
+template <typename R>
+__device__ __forceinline__ Consts<R> make_consts(const KProblem& p) {
+    Consts<R> c;
+    c.H = (R)p.H;
+    c.invH = (R)(1.0 / p.H);
+    c.eps = (R)p.eps_reg;
+    c.Hme = (R)(p.H - p.eps_reg);
+    c.ks = (R)p.ks;
+    c.acoef = (R)(0.75 * p.ks * p.ks / p.H);
+    c.inv_kt = (R)(1.0 / p.kappa_tau);
+    c.su_h = (R)p.sigma_u;
+    c.lam_h = (R)(1.0 / p.tau);
+    return c;
+}
+
+// sigma_U and lambda at X (Eqs. 5, 7).
+template <typename R, int PROF>
+__device__ __forceinline__ void profile_at(const Consts<R>& c, R x, R& su, R& lam) {
+    if (PROF == KPROFILE_HOMOGENEOUS) {
+        su = c.su_h;
+        lam = c.lam_h;
+    } else {
+        const R xc = fmin(fmax(x, c.eps), c.Hme);
+        const R s = (c.H - xc) * c.invH;
+        const R sq = Math<R>::sqrt_(s);
+        su = c.ks * Math<R>::sqrt_(s * sq);           // kappa_sigma u_* s^(3/4)
+        lam = su * c.inv_kt * Math<R>::rcp(xc);        // sigma_U / (kappa_tau X)
+    }
+}
+
+// sigma_U, lambda and the drift coefficients a, b at X.
+template <typename R, int PROF>
+__device__ __forceinline__ void coeffs_at(const Consts<R>& c, R x, R& su, R& lam, R& a, R& b) {
+    if (PROF == KPROFILE_HOMOGENEOUS) {
+        su = c.su_h;
+        lam = c.lam_h;
+        a = (R)0;
+        b = (R)0;
+    } else {
+        const R xc = fmin(fmax(x, c.eps), c.Hme);
+        const R s = (c.H - xc) * c.invH;
+        const R sq = Math<R>::sqrt_(s);
+        su = c.ks * Math<R>::sqrt_(s * sq);
+        lam = su * c.inv_kt * Math<R>::rcp(xc);
+        const bool inside = (x >= c.eps) && (x <= c.Hme);   // then xc == x
+        a = inside ? c.acoef * sq : (R)0;
+        b = inside ? (R)0.75 * Math<R>::rcp(c.H - x) : (R)0;
+    }
+}
+
+template <typename R, int PROF>
+__device__ __forceinline__ void drift_at(const Consts<R>& c, R x, R& a, R& b) {
+    if (PROF == KPROFILE_HOMOGENEOUS) {
+        a = (R)0;
+        b = (R)0;
+    } else {
+        const bool inside = (x >= c.eps) && (x <= c.Hme);
+        const R s = (c.H - x) * c.invH;
+        a = inside ? c.acoef * Math<R>::sqrt_(s) : (R)0;
+        b = inside ? (R)0.75 * Math<R>::rcp(c.H - x) : (R)0;
+    }
+}
+
+template <typename R>
+struct Path {
+    R x, u;
+    uint32_t sgn;   // reflection sign S as a sign-bit mask (0: S = +1)
+    R a, b;         // drift coefficients at x (BAOAB carries them to the next step)
+    bool bad;
+};
+
+// Fold into [0, H]; 0 and H are inside. More than kFoldMax reflections in one fold
+// means the step ran away: the path becomes NaN and is counted as non-finite.
+template <typename R>
+__device__ __forceinline__ void fold(Path<R>& p, R H) {
+    if (p.x < (R)0 || p.x > H) {
+        int count = 0;
+        do {
+            if (++count > kFoldMax) {
+                p.x = (R)NAN;
+                p.u = (R)NAN;
+                p.bad = true;
+                break;
+            }
+            p.x = (p.x < (R)0) ? -p.x : (R)2 * H - p.x;
+            p.u = -p.u;
+            p.sgn ^= kSignBit;
+        } while (p.x < (R)0 || p.x > H);
+    }
+}
+
+// One step of size h. COARSE: xi is the combined extended noise and the physical noise
+// is S xi; otherwise xi is the physical noise and `tilde` receives S xi. `w` receives
+// e^{-lambda h} of the O-step (GL, BAOAB).
+template <typename R, int INTEG, int PROF, bool COARSE>
+__device__ __forceinline__ void step(const Consts<R>& c, Path<R>& p, R h, R hh, R xi,
+                                     R& tilde, R& w) {
+    if (INTEG == KINTEG_SE) {                                        // Eq. (8)
+        R su, lam, a, b;
+        coeffs_at<R, PROF>(c, p.x, su, lam, a, b);
+        const R noise = COARSE ? Math<R>::flip(xi, p.sgn) : xi;
+        if (!COARSE) tilde = Math<R>::flip(xi, p.sgn);
+        const R amp = su * Math<R>::sqrt_((R)2 * lam * h);             // sigma sqrt(h)
+        const R drift = -(a + b * p.u * p.u);
+        p.u = ((R)1 - lam * h) * p.u + drift * h + amp * noise;
+        p.x = p.x + p.u * h;
+        fold(p, c.H);
+        w = (R)1;
+    } else if (INTEG == KINTEG_GL) {                                 // Eq. (9)
+        R su, lam, a, b;
+        coeffs_at<R, PROF>(c, p.x, su, lam, a, b);
+        const R noise = COARSE ? Math<R>::flip(xi, p.sgn) : xi;
+        if (!COARSE) tilde = Math<R>::flip(xi, p.sgn);
+        const R e1 = Math<R>::expm1_(-lam * h);
+        w = (R)1 + e1;
+        const R amp = su * Math<R>::sqrt_(-e1 * ((R)2 + e1));
+        const R us = w * p.u + amp * noise;                          // O
+        p.u = us - (a + b * us * us) * h;                            // B at (X_n, U*)
+        p.x = p.x + p.u * h;                                         // A
+        fold(p, c.H);
+    } else {                                                         // Eq. (10)
+        p.u = p.u - (p.a + p.b * p.u * p.u) * hh;                    // B at (X_n, U_n)
+        p.x = p.x + p.u * hh;                                        // A
+        fold(p, c.H);
+        R su, lam;
+        profile_at<R, PROF>(c, p.x, su, lam);
+        const R noise = COARSE ? Math<R>::flip(xi, p.sgn) : xi;
+        if (!COARSE) tilde = Math<R>::flip(xi, p.sgn);
+        const R e1 = Math<R>::expm1_(-lam * h);
+        w = (R)1 + e1;
+        const R amp = su * Math<R>::sqrt_(-e1 * ((R)2 + e1));
+        p.u = w * p.u + amp * noise;                                 // O at X_{n+1/2}
+        p.x = p.x + p.u * hh;                                        // A
+        fold(p, c.H);
+        drift_at<R, PROF>(c, p.x, p.a, p.b);
+        p.u = p.u - (p.a + p.b * p.u * p.u) * hh;                    // B at (X_{n+1}, U*)
+    }
+}
+
+// Initial state shared by both paths of a sample.
+template <typename R, int PROF>
+__device__ __forceinline__ void initial_state(const KProblem& kp, const Consts<R>& c,
+                                              const Stream& st, R& x0, R& u0) {
+    if (kp.release == KRELEASE_FIXED_W) {
+        x0 = (R)kp.z0;
+        u0 = (R)kp.w0;
+        return;
+    }
+    R z0, z1;
+    Normals<R>::pair(philox(st, kBlockInitW), z0, z1);
+    if (kp.release == KRELEASE_GAUSSIAN_W) {
+        x0 = (R)kp.z0;
+        u0 = (R)kp.su_z0 * z0;
+        return;
+    }
+    const Words wx = philox(st, kBlockInitX);
+    if (sizeof(R) == 8)
+        x0 = (R)(kp.H * uniform64(wx.r1, wx.r0));
+    else
+        x0 = (R)kp.H * (R)uniform32(wx.r1);
+    R su, lam;
+    profile_at<R, PROF>(c, x0, su, lam);
+    u0 = su * z0;
+}
+
+template <typename R, int INTEG, int PROF>
+__device__ __forceinline__ void init_path(const Consts<R>& c, Path<R>& p, R x0, R u0) {
+    p.x = x0;
+    p.u = u0;
+    p.sgn = 0u;
+    p.bad = false;
+    p.a = (R)0;
+    p.b = (R)0;
+    if (INTEG == KINTEG_BAOAB) drift_at<R, PROF>(c, x0, p.a, p.b);
+}
+
+// Runs one sample of `level`. Returns the terminal fine and coarse states.
+template <typename R, int INTEG, int PROF>
+__device__ __forceinline__ void run_sample(const KProblem& kp, const Consts<R>& c, int level,
+                                           uint64_t sample, Path<R>& f, Path<R>& g) {
+    const Stream st = make_stream(kp.seed, kp.stream_id, level, sample);
+    R x0, u0;
+    initial_state<R, PROF>(kp, c, st, x0, u0);
+    init_path<R, INTEG, PROF>(c, f, x0, u0);
+    init_path<R, INTEG, PROF>(c, g, x0, u0);
+    const uint32_t M = (uint32_t)kp.M0 << level;                 // M_l = M_0 2^l
+    const double hd = kp.T / (double)M;                           // h_l = T / M_l
+    const R h = (R)hd, hh = (R)(0.5 * hd), h2 = (R)(2.0 * hd);
+    R tilde_a, tilde_b, w_a, w_b, z0, z1;
+    if (level == 0) {
+        for (uint32_t m = 0; m < M / 2; ++m) {
+            Normals<R>::pair(philox(st, m), z0, z1);
+            step<R, INTEG, PROF, false>(c, f, h, hh, z0, tilde_a, w_a);
+            step<R, INTEG, PROF, false>(c, f, h, hh, z1, tilde_b, w_b);
+        }
+        if (M & 1u) {
+            Normals<R>::pair(philox(st, M / 2), z0, z1);
+            step<R, INTEG, PROF, false>(c, f, h, hh, z0, tilde_a, w_a);
+        }
+        return;
+    }
+    for (uint32_t m = 0; m < M / 2; ++m) {
+        Normals<R>::pair(philox(st, m), z0, z1);
+        step<R, INTEG, PROF, false>(c, f, h, hh, z0, tilde_a, w_a);   // fine step 2m
+        step<R, INTEG, PROF, false>(c, f, h, hh, z1, tilde_b, w_b);   // fine step 2m+1
+        R xi_c;
+        if (INTEG == KINTEG_SE)
+            xi_c = (tilde_a + tilde_b) * (R)0.70710678118654752440;  // Eq. (18)
+        else
+            xi_c = (w_a * tilde_a + tilde_b) * Math<R>::rsqrt(w_a * w_a + (R)1);   // Eq. (19)
+        R unused_t, unused_w;
+        step<R, INTEG, PROF, true>(c, g, h2, h, xi_c, unused_t, unused_w);
+    }
+}
+
+// Quantity of interest in FP64 (Sec. 2, Sec. 5).
+__device__ __forceinline__ double g_r(const KProblem& kp, double s) {
+    if (s < -1.0) return 1.0;
+    if (s > 1.0) return 0.0;
+    double v = 0.0;
+    for (int k = kp.ncoef - 1; k >= 0; --k) v = fma(v, s, kp.coef[k]);
+    return v;
+}
+
+__device__ __forceinline__ double qoi(const KProblem& kp, double x, double u) {
+    switch (kp.qoi_kind) {
+        case KQOI_MEAN_Z: return x;
+        case KQOI_VELOCITY: return u;
+        case KQOI_VELOCITY_SQ: return u * u;
+        case KQOI_P_ABOVE:
+            if (kp.r == 0) return x > kp.qa ? 1.0 : 0.0;
+            return 1.0 - g_r(kp, (x - kp.qa) * kp.inv_delta);
+        default:   // KQOI_P_BOX, Eq. (34) / Eq. (37)
+            if (kp.r == 0) return (x <= kp.qb ? 1.0 : 0.0) - (x <= kp.qa ? 1.0 : 0.0);
+            return g_r(kp, (x - kp.qb) * kp.inv_delta) - g_r(kp, (x - kp.qa) * kp.inv_delta);
+    }
+}
+
+}  // namespace ldm

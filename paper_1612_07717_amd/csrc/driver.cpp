@@ -1,0 +1,319 @@
+// driver.cpp -- the adaptive MLMC driver (host, FP64) and mlmc_estimate.
+//
+// The mean square error of the estimator (Eq. 17) is bias^2 + sum_l V_l / N_l; each
+// part is held below eps^2 / 2 (Sec. 3.2, Sec. 6). For a cost C_l = M_l per sample
+// (condition (iv) of the theorem of Sec. 3.3) the sample counts minimising
+// sum_l N_l C_l under sum_l V_l / N_l = eps^2 / 2 are
+//     N_l = 2 eps^-2 sqrt(V_l / C_l) sum_k sqrt(V_k C_k)
+// (Lagrange multipliers; Giles 2008, cited in Sec. 6). The bias is estimated from the
+// finest level means with E[P_l - P] ~ c h_l^alpha (Sec. 6): then
+// E[P_L - P] ~ Yhat_L / (2^alpha - 1), and Yhat_{L-1} 2^-alpha estimates the same.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "host_common.hpp"
+
+using namespace ldm;
+
+namespace {
+
+double cost_of_level(int32_t M0, int32_t l) { return std::ldexp((double)M0, l); }
+
+// Samples needed on each level 0..L for the variance budget, minus those already
+// drawn (0 if none are needed).
+void variance_rule(const ld_plan_in* in, int32_t L, const double* V, double eps_abs,
+                   uint64_t* dn) {
+    double weighted = 0.0;
+    for (int32_t l = 0; l <= L; ++l) weighted += std::sqrt(V[l] * cost_of_level(in->M0, l));
+    const double scale = 2.0 * weighted / (eps_abs * eps_abs);
+    for (int32_t l = 0; l <= L; ++l) {
+        const double want = std::ceil(scale * std::sqrt(V[l] / cost_of_level(in->M0, l)));
+        const uint64_t have = (l <= in->L) ? in->n[l] : 0;
+        if (!(want > (double)have))
+            dn[l] = 0;
+        else if (want >= 4.0e18)
+            dn[l] = (uint64_t)1 << 62;
+        else
+            dn[l] = (uint64_t)want - have;
+    }
+}
+
+double fitted_alpha(const double* Yhat, int32_t L) {
+    // least-squares slope of -log2 |Yhat_l| against l over l = 1..L
+    int cnt = 0;
+    double sx = 0, sy = 0, sxx = 0, sxy = 0;
+    for (int32_t l = 1; l <= L; ++l) {
+        const double a = std::fabs(Yhat[l]);
+        if (!(a > 0.0)) continue;
+        const double y = -std::log2(a);
+        sx += l;
+        sy += y;
+        sxx += (double)l * l;
+        sxy += l * y;
+        ++cnt;
+    }
+    double alpha = 1.0;
+    if (cnt >= 2) {
+        const double den = cnt * sxx - sx * sx;
+        if (den > 0) alpha = (cnt * sxy - sx * sy) / den;
+    }
+    return std::min(std::max(alpha, 0.5), 2.0);
+}
+
+struct HostSums {
+    double s[4] = {0, 0, 0, 0}, c[4] = {0, 0, 0, 0};
+    uint64_t n = 0, bad = 0;
+};
+
+void merge_into(HostSums& acc, const ld_level_sums& add) {
+    for (int k = 0; k < 4; ++k) {
+        const double t = acc.s[k] + add.s[k];
+        const double big = std::fabs(acc.s[k]) >= std::fabs(add.s[k]) ? acc.s[k] : add.s[k];
+        const double small = std::fabs(acc.s[k]) >= std::fabs(add.s[k]) ? add.s[k] : acc.s[k];
+        acc.c[k] = (acc.c[k] + add.c[k]) + ((big - t) + small);
+        acc.s[k] = t;
+    }
+    acc.n += add.n;
+    acc.bad += add.n_nonfinite;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mlmc_plan(const ld_plan_in* in, ld_plan_out* out) {
+    if (in == nullptr || out == nullptr) return fail(LD_EINVAL, "NULL argument");
+    if (in->L < 0 || in->L >= LD_MAX_LEVELS || in->M0 < 1 || !(in->eps > 0))
+        return fail(LD_EINVAL, "invalid planner input");
+    std::memset(out, 0, sizeof *out);
+    const int32_t L = in->L;
+    double estimate = 0.0, stat_var = 0.0;
+    for (int32_t l = 0; l <= L; ++l) {
+        const double n = (double)in->n[l];
+        const double mean = in->n[l] > 0 ? in->sum1[l] / n : 0.0;
+        double var = in->n[l] > 1 ? (in->sum2[l] - n * mean * mean) / (n - 1.0) : 0.0;
+        if (!(var > 0.0)) var = 0.0;   // unbiased sample variance, clamped at 0
+        out->Yhat[l] = mean;
+        out->V[l] = var;
+        estimate += mean;
+        if (in->n[l] > 0) stat_var += var / n;
+    }
+    out->estimate = estimate;
+    out->stat_var = stat_var;
+    out->eps_abs = in->eps_is_relative ? in->eps * std::fabs(estimate) : in->eps;
+    const double alpha = (in->alpha > 0.0) ? in->alpha : fitted_alpha(out->Yhat, L);
+    out->alpha = alpha;
+    const double r = std::pow(2.0, alpha);
+    out->bias_est = (L >= 1) ? std::max(std::fabs(out->Yhat[L]), std::fabs(out->Yhat[L - 1]) / r) / (r - 1.0)
+                             : 0.0;
+    out->L = L;
+    if (in->fixed_N) {
+        out->status = 1;
+        return LD_OK;
+    }
+    if (!(out->eps_abs > 0.0)) {   // relative eps of a zero estimate: nothing to aim at
+        out->status = 2;
+        return LD_OK;
+    }
+    variance_rule(in, L, out->V, out->eps_abs, out->dn);
+    bool more = false;
+    for (int32_t l = 0; l <= L; ++l)
+        if ((double)out->dn[l] > 0.01 * (double)in->n[l]) more = true;
+    if (more) {
+        out->status = 0;
+        return LD_OK;
+    }
+    for (int32_t l = 0; l <= L; ++l) out->dn[l] = 0;
+    if (in->fixed_L >= 0 || L < 1 || out->bias_est <= out->eps_abs / std::sqrt(2.0)) {
+        out->status = 1;
+        return LD_OK;
+    }
+    if (L >= in->L_max || L + 1 >= LD_MAX_LEVELS) {
+        out->status = 2;
+        return LD_OK;
+    }
+    double V[LD_MAX_LEVELS];
+    for (int32_t l = 0; l <= L; ++l) V[l] = out->V[l];
+    V[L + 1] = V[L] / 4.0;   // variance decay h^2 (condition (iii))
+    variance_rule(in, L + 1, V, out->eps_abs, out->dn);
+    out->dn[L + 1] = std::max(out->dn[L + 1], in->N_init);
+    out->L = L + 1;
+    out->status = 0;
+    return LD_OK;
+}
+
+void mlmc_estimate_default_opts(ld_estimate_opts* o) {
+    if (o == nullptr) return;
+    std::memset(o, 0, sizeof *o);
+    o->release.kind = LD_RELEASE_FIXED_W;   // the paper's Sec. 6 release: 50 m, 0.1 m/s
+    o->release.z0 = 50.0;
+    o->release.w0 = 0.1;
+    o->T = 1000.0;
+    o->M0 = 40;
+    o->L_min = 2;
+    o->L_max = 20;
+    o->fixed_L = -1;
+    o->fixed_N = 0;
+    o->eps_is_relative = 0;
+    o->N_init = 10000;
+    o->alpha = 1.0;
+    o->precision = LD_FP64;
+    o->max_iter = 100;
+}
+
+size_t mlmc_estimate_workspace(void) {
+    // per level: its sums plus at most the blocks plan_item gives any range
+    uint32_t spl, nb;
+    plan_item(~(uint64_t)0 >> 2, &spl, &nb);
+    return (size_t)LD_MAX_LEVELS * (1 + (size_t)nb) * sizeof(ld_level_sums);
+}
+
+int mlmc_estimate(double eps, const ld_qoi* qoi, ld_integrator integrator, const ld_profile* profile,
+                  const ld_estimate_opts* opts_in, ld_estimate_result* out) {
+    const auto t_start = std::chrono::steady_clock::now();
+    if (qoi == nullptr || profile == nullptr || out == nullptr) return fail(LD_EINVAL, "NULL argument");
+    if (!(eps > 0.0) || !std::isfinite(eps)) return fail(LD_EINVAL, "eps must be positive");
+    ld_estimate_opts opts;
+    if (opts_in)
+        opts = *opts_in;
+    else
+        mlmc_estimate_default_opts(&opts);
+    std::memset(out, 0, sizeof *out);
+    ld_problem prob;
+    std::memset(&prob, 0, sizeof prob);
+    prob.profile = *profile;
+    prob.release = opts.release;
+    prob.qoi = *qoi;
+    prob.T = opts.T;
+    prob.M0 = opts.M0;
+    prob.stream_id = opts.stream_id;
+    prob.seed = opts.seed;
+    int rc = validate_problem(&prob);
+    if (rc != LD_OK) return rc;
+    const int32_t L0 = opts.fixed_L >= 0 ? opts.fixed_L : opts.L_min;
+    if (L0 < 0 || L0 >= LD_MAX_LEVELS || opts.L_max < L0 || opts.L_max >= LD_MAX_LEVELS)
+        return fail(LD_EINVAL, "need 0 <= L_min <= L_max < LD_MAX_LEVELS");
+    if (opts.N_init < 2) return fail(LD_EINVAL, "N_init must be >= 2");
+    rc = check_stability(&prob, integrator, 0);
+    if (rc != LD_OK) return rc;
+
+    hipStream_t stream = (hipStream_t)opts.hip_stream;
+    const size_t ws_need = mlmc_estimate_workspace();
+    void* ws = opts.d_workspace;
+    bool own_ws = false;
+    if (ws == nullptr) {
+        if (hipMalloc(&ws, ws_need) != hipSuccess) return fail(LD_EDEVICE, "hipMalloc of the workspace failed");
+        own_ws = true;
+    } else if (opts.workspace_bytes < ws_need) {
+        return fail(LD_ENOMEM, "workspace smaller than mlmc_estimate_workspace()");
+    }
+    ld_level_sums* d_sums = (ld_level_sums*)ws;
+    void* d_partials = (void*)(d_sums + LD_MAX_LEVELS);
+    const size_t partial_bytes = ws_need - LD_MAX_LEVELS * sizeof(ld_level_sums);
+
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    const bool timing = hipEventCreate(&ev0) == hipSuccess && hipEventCreate(&ev1) == hipSuccess;
+
+    std::vector<HostSums> sums(LD_MAX_LEVELS);
+    uint64_t drawn[LD_MAX_LEVELS] = {0};
+    uint64_t dn[LD_MAX_LEVELS] = {0};
+    ld_plan_in pin;
+    std::memset(&pin, 0, sizeof pin);
+    pin.L = L0;
+    pin.M0 = opts.M0;
+    pin.eps = eps;
+    pin.alpha = opts.alpha;
+    pin.eps_is_relative = opts.eps_is_relative;
+    pin.L_max = opts.L_max;
+    pin.fixed_L = opts.fixed_L;
+    pin.fixed_N = opts.fixed_N;
+    pin.N_init = opts.N_init;
+    for (int32_t l = 0; l <= L0; ++l) dn[l] = opts.N_init;
+    ld_plan_out plan;
+    std::memset(&plan, 0, sizeof plan);
+    const int max_iter = opts.max_iter > 0 ? opts.max_iter : 100;
+    int iter = 0;
+    double device_s = 0.0;
+    ld_level_sums host_batch[LD_MAX_LEVELS];
+    rc = LD_OK;
+    for (;;) {
+        ld_level_range ranges[LD_MAX_LEVELS];
+        int32_t nr = 0;
+        for (int32_t l = 0; l <= pin.L; ++l) {
+            if (dn[l] == 0) continue;
+            ranges[nr].level = l;
+            ranges[nr].reserved = 0;
+            ranges[nr].sample_begin = drawn[l];
+            ranges[nr].n_samples = dn[l];
+            ++nr;
+        }
+        if (nr > 0) {
+            if (timing) (void)hipEventRecord(ev0, stream);
+            rc = run_batch(&prob, integrator, opts.precision, ranges, nr, d_sums, d_partials,
+                           partial_bytes, nullptr, stream);
+            if (rc != LD_OK) break;
+            if (timing) (void)hipEventRecord(ev1, stream);
+            if (hipMemcpyAsync(host_batch, d_sums, nr * sizeof(ld_level_sums), hipMemcpyDeviceToHost,
+                               stream) != hipSuccess ||
+                hipStreamSynchronize(stream) != hipSuccess) {
+                rc = fail(LD_EDEVICE, std::string("level sums failed: ") + hipGetErrorString(hipGetLastError()));
+                break;
+            }
+            if (timing) {
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, ev0, ev1) == hipSuccess) device_s += ms * 1e-3;
+            }
+            out->launches += 1;
+            for (int32_t j = 0; j < nr; ++j) {
+                merge_into(sums[ranges[j].level], host_batch[j]);
+                drawn[ranges[j].level] += ranges[j].n_samples;
+            }
+        }
+        for (int32_t l = 0; l <= pin.L; ++l) {
+            pin.n[l] = sums[l].n;
+            pin.sum1[l] = sums[l].s[0] + sums[l].c[0];
+            pin.sum2[l] = sums[l].s[1] + sums[l].c[1];
+        }
+        mlmc_plan(&pin, &plan);
+        ++iter;
+        if (plan.status != 0 || iter >= max_iter) break;
+        pin.L = plan.L;
+        std::memcpy(dn, plan.dn, sizeof dn);
+    }
+    if (timing) {
+        (void)hipEventDestroy(ev0);
+        (void)hipEventDestroy(ev1);
+    }
+    if (own_ws) (void)hipFree(ws);
+    if (rc != LD_OK) return rc;
+
+    out->estimate = plan.estimate;
+    out->eps_abs = plan.eps_abs;
+    out->bias_est = plan.bias_est;
+    out->stat_var = plan.stat_var;
+    out->rmse_est = std::sqrt(plan.bias_est * plan.bias_est + plan.stat_var);
+    out->alpha = plan.alpha;
+    out->L = plan.L;
+    out->iterations = iter;
+    out->status = plan.status == 0 ? 2 : plan.status;
+    for (int32_t l = 0; l <= plan.L; ++l) {
+        out->N[l] = drawn[l];
+        out->n_nonfinite += sums[l].bad;
+        out->Yhat[l] = plan.Yhat[l];
+        out->V[l] = plan.V[l];
+        const double M = cost_of_level(opts.M0, l);
+        out->fine_steps += (double)drawn[l] * M;
+        out->integrator_steps += (double)drawn[l] * (l == 0 ? M : 1.5 * M);
+    }
+    out->device_seconds = device_s;
+    out->wall_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    if (out->n_nonfinite > 0) return fail(LD_ENONFINITE, "some samples were non-finite");
+    return out->status == 1 ? LD_OK : LD_WARN_NOT_CONVERGED;
+}
+
+}  // extern "C"

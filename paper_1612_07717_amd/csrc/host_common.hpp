@@ -1,0 +1,42 @@
+// host_common.hpp -- host-side helpers shared by the C ABI translation units.
+#pragma once
+
+#include <string>
+
+#include "ld_internal.hpp"
+
+namespace ldm {
+
+void set_error(const std::string& msg);
+int fail(int status, const std::string& msg);
+
+// Validates a problem; returns LD_OK or LD_EINVAL (message set).
+int validate_problem(const ld_problem* p);
+// Symplectic Euler is stable only for lambda h < 2 (Sec. 3.1); returns LD_EUNSTABLE if
+// a step of `level` violates it, else LD_OK.
+int check_stability(const ld_problem* p, ld_integrator integ, int32_t level);
+// Regularised sigma_U(x) of the profile (Eqs. 5, 7).
+double sigma_u_at(const ld_profile& prof, double x);
+// lambda_max over [0, H].
+double lambda_max(const ld_profile& prof);
+
+// Fills the kernel-side problem (FP64 parameters, smoothing coefficients).
+int make_kproblem(const ld_problem* p, ld_integrator integ, KProblem* kp);
+
+// Smoothing polynomial p_r of Eq. (35): coef[0..r+1], r in 1..8 (smoothing.cpp).
+int smoothing_coefficients(int r, double* coef);
+
+// Launch plan of one (level, range): samples per lane and block count.
+void plan_item(uint64_t n_samples, uint32_t* spl, uint32_t* n_blocks);
+
+// Builds the items of a batch (most expensive level first), returns total blocks.
+int build_batch(const ld_problem* p, ld_integrator integ, ld_precision prec,
+                const ld_level_range* ranges, int32_t n_ranges, KArgs* args,
+                uint32_t* total_blocks);
+
+// Runs a batch: K1 + merge; d_out gets one ld_level_sums per range.
+int run_batch(const ld_problem* p, ld_integrator integ, ld_precision prec,
+              const ld_level_range* ranges, int32_t n_ranges, ld_level_sums* d_out,
+              void* d_workspace, size_t workspace_bytes, double* d_dump, void* stream);
+
+}  // namespace ldm

@@ -1,0 +1,57 @@
+// ld_internal.hpp -- structures shared by the host runtime and the kernels.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/ldmlmc.h"
+
+namespace ldm {
+
+enum { KINTEG_SE = 0, KINTEG_GL = 1, KINTEG_BAOAB = 2 };
+enum { KPROFILE_HOMOGENEOUS = 0, KPROFILE_NEUTRAL = 1 };
+enum { KRELEASE_FIXED_W = 0, KRELEASE_GAUSSIAN_W = 1, KRELEASE_WELL_MIXED = 2 };
+enum { KQOI_MEAN_Z = 0, KQOI_P_ABOVE = 1, KQOI_P_BOX = 2, KQOI_VELOCITY = 3, KQOI_VELOCITY_SQ = 4 };
+
+constexpr int kFoldMax = 16;      // reflections allowed in one fold before a path is declared runaway
+constexpr int kBlock = 256;       // threads per block of the level kernel (4 wave64)
+constexpr int kMaxItems = 40;     // (level, range) items per launch
+constexpr int kMaxCoef = 10;      // smoothing polynomial p_r, r <= 8
+
+// Problem parameters in FP64, prepared on the host (kernel argument).
+struct KProblem {
+    double H, eps_reg, ks, kappa_tau, sigma_u, tau, T;
+    double z0, w0, su_z0;          // release; su_z0 = regularised sigma_U(z0)
+    double qa, qb, inv_delta;
+    double coef[kMaxCoef];
+    int32_t integ, profile, release, qoi_kind, r, ncoef, M0;
+    uint32_t stream_id;
+    uint64_t seed;
+};
+
+// One (level, sample range) of a launch. Blocks [block_begin, block_begin + n_blocks)
+// cover it; each lane of a block handles `spl` samples.
+struct KItem {
+    int32_t level;
+    uint32_t spl;
+    uint32_t block_begin;
+    uint32_t n_blocks;
+    uint64_t sample_begin;
+    uint64_t n_samples;
+    uint32_t out_slot;
+    uint32_t pad;
+};
+
+struct KArgs {
+    KProblem prob;
+    int32_t n_items;
+    int32_t precision;
+    KItem items[kMaxItems];
+};
+
+// Host-side launch of the level kernels (kernels.hip). partials must hold
+// total_blocks ld_level_sums; out holds one per item (indexed by out_slot).
+int launch_levels(const KArgs& args, uint32_t total_blocks, ld_level_sums* d_partials,
+                  ld_level_sums* d_out, double* d_dump, void* stream);
+
+}  // namespace ldm

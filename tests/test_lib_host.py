@@ -1,0 +1,161 @@
+"""Host-side tests of the HIP library (no GPU needed).
+
+- the library loads and exports every function include/ldmlmc.h declares;
+- the ctypes structs of the binding match the C layout (sizes and offsets printed by a
+  small C program compiled against the header);
+- the library's planner (mlmc_plan) and the oracle's take the same decisions on the
+  same inputs (the two are independent implementations of the algorithm);
+- argument validation and the stability check reject bad input before any device use.
+"""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+import paper_1612_07717_amd as ld
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ldmlmc.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(ld.LIB_PATH):
+        from paper_1612_07717_amd import build
+        build.build()
+    return ld.load()
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_0-9]+\s*\*?\s*\b([a-z_0-9]+)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n.startswith(("mlmc_", "ld_"))))
+
+
+def test_exports_every_declared_function(lib):
+    declared = _declared_functions()
+    assert len(declared) >= 11
+    assert sorted(declared) == sorted(ld.EXPORTED)
+    out = subprocess.run(["nm", "-D", "--defined-only", ld.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (\S+)", out))
+    for name in declared:
+        assert name in exported, name
+        assert hasattr(lib, name)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    structs = {"ld_profile": ld.Profile, "ld_qoi": ld.Qoi, "ld_release": ld.Release,
+               "ld_problem": ld.Problem, "ld_level_sums": ld.LevelSums,
+               "ld_level_range": ld.LevelRange, "ld_plan_in": ld.PlanIn,
+               "ld_plan_out": ld.PlanOut, "ld_estimate_opts": ld.EstimateOpts,
+               "ld_estimate_result": ld.EstimateResult}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ldmlmc.h"', "int main(void){"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in py._fields_:
+            lines.append(f'printf("{cname}.{field} %zu\\n", offsetof({cname}, {field}));')
+    lines.append("return 0;}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    got = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True,
+                                                              text=True, check=True).stdout.splitlines())
+    for cname, py in structs.items():
+        assert int(got[f"{cname} size"]) == C.sizeof(py), cname
+        for field, _ in py._fields_:
+            assert int(got[f"{cname}.{field}"]) == getattr(py, field).offset, (cname, field)
+
+
+def _random_plan_inputs(rng, n_cases):
+    for _ in range(n_cases):
+        L = int(rng.integers(0, 8))
+        n = [int(rng.integers(2, 200000)) for _ in range(L + 1)]
+        V = [float(10.0 ** rng.uniform(-5, 3)) * 4.0 ** -l for l in range(L + 1)]
+        mean = [float(rng.normal(0, 3)) * 2.0 ** -l for l in range(L + 1)]
+        s1 = [m * k for m, k in zip(mean, n)]
+        s2 = [v * (k - 1) + k * m * m for v, k, m in zip(V, n, mean)]
+        yield dict(L=L, n=n, sum1=s1, sum2=s2, M0=int(rng.choice([8, 40, 80])),
+                   eps=float(10.0 ** rng.uniform(-3, 1)),
+                   eps_is_relative=int(rng.integers(0, 2)), L_max=int(rng.integers(L, 12)),
+                   fixed_L=int(rng.choice([-1, -1, L])), fixed_N=int(rng.integers(0, 10) == 0),
+                   N_init=int(rng.choice([1000, 10000])), alpha=float(rng.choice([1.0, 2.0, 0.0])))
+
+
+def test_planner_matches_oracle_planner(lib, orc):
+    rng = np.random.default_rng(11)
+    checked = 0
+    for d in _random_plan_inputs(rng, 3000):
+        a, b = ld.plan(d), orc.plan(d)
+        assert a["status"] == b["status"] and a["L"] == b["L"], d
+        assert a["dn"] == b["dn"], d
+        for k in ("estimate", "eps_abs", "alpha", "bias_est", "stat_var"):
+            assert a[k] == pytest.approx(b[k], rel=1e-12, abs=1e-300), (k, d)
+        assert np.allclose(a["V"], b["V"], rtol=1e-12, atol=0)
+        checked += 1
+    assert checked == 3000
+
+
+def test_planner_rejects_bad_input(lib):
+    with pytest.raises(ld.LdError) as e:
+        ld.plan(dict(L=-1, n=[], sum1=[], sum2=[], M0=8, eps=1.0))
+    assert e.value.status == ld.LD_EINVAL
+    with pytest.raises(ld.LdError):
+        ld.plan(dict(L=1, n=[10, 10], sum1=[0, 0], sum2=[1, 1], M0=8, eps=0.0))
+
+
+def _call_level_sums(lib, cfg, level=0, n=100, ws_bytes=None, integ=None):
+    p = ld.make_problem(cfg)
+    ws_bytes = ld.level_sums_workspace(n) if ws_bytes is None else ws_bytes
+    fake = C.c_void_p(0x1000)   # never dereferenced: validation fails first
+    return lib.mlmc_level_sums(C.byref(p), ld.INTEGRATORS[integ or cfg["integrator"]], 0, level, 0,
+                               n, fake, fake, ws_bytes, None)
+
+
+def test_validation_rejects_bad_problems_without_device(lib):
+    good = W.neutral(300.0, "GL")
+    bad = [dict(good, H=-1.0), dict(good, eps_reg=600.0), dict(good, eps_reg=0.0),
+           dict(good, kappa_tau=0.0), dict(good, z0=1200.0), dict(good, T=0.0),
+           dict(good, M0=0), dict(good, stream_id=1 << 24),
+           dict(good, qoi="p_box", r=9, delta=100.0), dict(good, qoi="p_box", r=4, delta=0.0),
+           dict(W.homogeneous(), tau=0.0), dict(W.homogeneous(), sigma_u=-1.0)]
+    for cfg in bad:
+        assert _call_level_sums(lib, cfg) == ld.LD_EINVAL, cfg
+    assert _call_level_sums(lib, good, level=32) == ld.LD_EINVAL
+    assert _call_level_sums(lib, dict(good, M0=1 << 20), level=12) == ld.LD_EINVAL   # M > 2^31
+
+
+def test_symplectic_euler_stability_check(lib):
+    """Sec. 3.1: SE needs lambda h < 2. At eps_reg = 10 m, M_0 = 8 (h = 125 s) violates it
+    (lambda_max h = 6.45); M_0 = 40 does not. The coarse step of level l is 2 h_l."""
+    assert _call_level_sums(lib, W.single_large("SE"), level=0) == ld.LD_EUNSTABLE
+    assert _call_level_sums(lib, W.single_large("SE"), level=2) == ld.LD_EUNSTABLE   # 2h = 62.5 s
+    assert _call_level_sums(lib, W.single_large("SE"), level=3, ws_bytes=0) == ld.LD_ENOMEM
+    assert _call_level_sums(lib, W.single_large("BAOAB"), level=0, ws_bytes=0) == ld.LD_ENOMEM
+    assert _call_level_sums(lib, W.neutral(500.0, "SE"), level=0, ws_bytes=0) == ld.LD_ENOMEM
+    # homogeneous c1: lambda h_0 = 1.25 < 2
+    assert _call_level_sums(lib, W.homogeneous(), level=0, ws_bytes=0) == ld.LD_ENOMEM
+
+
+def test_estimate_argument_errors(lib):
+    with pytest.raises(ld.LdError) as e:
+        ld.estimate(0.0, W.neutral(300.0, "GL"))
+    assert e.value.status == ld.LD_EINVAL
+    with pytest.raises(ld.LdError) as e:
+        ld.estimate(1.0, W.single_large("SE"))
+    assert e.value.status == ld.LD_EUNSTABLE
+    with pytest.raises(ld.LdError) as e:
+        ld.estimate(1.0, W.neutral(300.0, "GL"), L_min=5, L_max=3)
+    assert e.value.status == ld.LD_EINVAL
+
+
+def test_strerror_covers_all_codes(lib):
+    for code in (0, 1, -1, -2, -3, -4, -5, -6):
+        assert lib.ld_strerror(code).decode() != "unknown status"
+    assert lib.ld_strerror(-99).decode() == "unknown status"
