@@ -138,6 +138,13 @@ void plan_item(uint64_t n_samples, uint32_t* spl, uint32_t* n_blocks) {
     *n_blocks = (uint32_t)((n_samples + per_block * s - 1) / (per_block * s));
 }
 
+uint32_t max_blocks(uint64_t n_samples) {
+    uint32_t spl, nb;
+    plan_item(n_samples, &spl, &nb);
+    if (n_samples <= kPipeMaxSamples) nb = std::max<uint32_t>(nb, (uint32_t)((n_samples + 63) / 64));
+    return nb;
+}
+
 int build_batch(const ld_problem* p, ld_integrator integ, ld_precision prec,
                 const ld_level_range* ranges, int32_t n_ranges, KArgs* args,
                 uint32_t* total_blocks) {
@@ -159,6 +166,7 @@ int build_batch(const ld_problem* p, ld_integrator integ, ld_precision prec,
     std::stable_sort(order, order + n_ranges,
                      [&](int a, int b) { return ranges[a].level > ranges[b].level; });
     uint64_t blocks = 0;
+    const int32_t top_level = ranges[order[0]].level;
     for (int j = 0; j < n_ranges; ++j) {
         const ld_level_range& r = ranges[order[j]];
         if (r.level < 0 || r.level >= LD_MAX_LEVELS)
@@ -171,7 +179,17 @@ int build_batch(const ld_problem* p, ld_integrator integ, ld_precision prec,
         if (rc != LD_OK) return rc;
         KItem& it = args->items[j];
         it.level = r.level;
-        plan_item(r.n_samples, &it.spl, &it.n_blocks);
+        const uint64_t M = (uint64_t)p->M0 << r.level;
+        if (r.level >= 1 && r.n_samples <= kPipeMaxSamples && M >= kPipeMinSteps) {
+            // long paths and few samples: latency-bound, use the wave-specialised blocks
+            it.mode = KMODE_PIPE;
+            it.spl = 1;
+            it.n_blocks = (uint32_t)((r.n_samples + 63) / 64);
+        } else {
+            it.mode = KMODE_STREAM;
+            plan_item(r.n_samples, &it.spl, &it.n_blocks);
+        }
+        it.prio = (uint16_t)std::max(0, 3 - (top_level - r.level));
         it.block_begin = (uint32_t)blocks;
         it.sample_begin = r.sample_begin;
         it.n_samples = r.n_samples;
@@ -208,9 +226,7 @@ using namespace ldm;
 extern "C" {
 
 size_t mlmc_level_sums_workspace(uint64_t n_samples) {
-    uint32_t spl, nb;
-    plan_item(n_samples, &spl, &nb);
-    return ((size_t)nb + 1) * sizeof(ld_level_sums);
+    return ((size_t)max_blocks(n_samples) + 1) * sizeof(ld_level_sums);
 }
 
 int mlmc_level_sums(const ld_problem* problem, ld_integrator integrator, ld_precision precision,
@@ -228,11 +244,7 @@ int mlmc_level_sums(const ld_problem* problem, ld_integrator integrator, ld_prec
 size_t mlmc_level_sums_batch_workspace(const ld_level_range* ranges, int32_t n_ranges) {
     if (ranges == nullptr || n_ranges < 1) return 0;
     size_t total = 0;
-    for (int i = 0; i < n_ranges; ++i) {
-        uint32_t spl, nb;
-        plan_item(ranges[i].n_samples, &spl, &nb);
-        total += nb;
-    }
+    for (int i = 0; i < n_ranges; ++i) total += max_blocks(ranges[i].n_samples);
     return total * sizeof(ld_level_sums);
 }
 
@@ -248,8 +260,7 @@ int mlmc_level_samples(const ld_problem* problem, ld_integrator integrator, ld_p
                        int32_t level, uint64_t sample_begin, uint64_t n_samples, double* d_pf_pc,
                        void* d_workspace, size_t workspace_bytes, void* hip_stream) {
     if (d_pf_pc == nullptr && n_samples > 0) return fail(LD_EINVAL, "d_pf_pc is NULL");
-    uint32_t spl, nb;
-    plan_item(n_samples, &spl, &nb);
+    const uint32_t nb = max_blocks(n_samples);
     const size_t need = ((size_t)nb + 1) * sizeof(ld_level_sums);
     if (d_workspace == nullptr) return fail(LD_EINVAL, "d_workspace is NULL");
     if (workspace_bytes < need) return fail(LD_ENOMEM, "workspace smaller than required");

@@ -45,6 +45,10 @@ struct Math<float> {
     static __device__ __forceinline__ float flip(float v, uint32_t mask) {
         return __uint_as_float(__float_as_uint(v) ^ mask);
     }
+    // v_med3_f32: the median of (x, lo, hi) is x clamped to [lo, hi] for lo <= hi
+    static __device__ __forceinline__ float clamp_(float x, float lo, float hi) {
+        return __builtin_amdgcn_fmed3f(x, lo, hi);
+    }
     // expm1 by argument reduction x = k ln2 + r, |r| <= ln2/2 (Cody & Waite's two-part
     // ln2), the Taylor series of expm1(r) to degree 7 (truncation < 2e-8 relative), and
     // expm1(x) = 2^k expm1(r) + (2^k - 1), which has no cancellation for k != 0.
@@ -75,6 +79,9 @@ struct Math<double> {
         return __hiloint2double(__double2hiint(v) ^ (int)mask, __double2loint(v));
     }
     static __device__ __forceinline__ double expm1_(double x) { return expm1(x); }
+    static __device__ __forceinline__ double clamp_(double x, double lo, double hi) {
+        return fmin(fmax(x, lo), hi);
+    }
 };
 
 // Per-(problem, level) constants in the path precision.
@@ -109,7 +116,7 @@ __device__ __forceinline__ void profile_at(const Consts<R>& c, R x, R& su, R& la
         su = c.su_h;
         lam = c.lam_h;
     } else {
-        const R xc = fmin(fmax(x, c.eps), c.Hme);
+        const R xc = Math<R>::clamp_(x, c.eps, c.Hme);
         const R s = (c.H - xc) * c.invH;
         const R sq = Math<R>::sqrt_(s);
         su = c.ks * Math<R>::sqrt_(s * sq);           // kappa_sigma u_* s^(3/4)
@@ -126,7 +133,7 @@ __device__ __forceinline__ void coeffs_at(const Consts<R>& c, R x, R& su, R& lam
         a = (R)0;
         b = (R)0;
     } else {
-        const R xc = fmin(fmax(x, c.eps), c.Hme);
+        const R xc = Math<R>::clamp_(x, c.eps, c.Hme);
         const R s = (c.H - xc) * c.invH;
         const R sq = Math<R>::sqrt_(s);
         su = c.ks * Math<R>::sqrt_(s * sq);
@@ -162,8 +169,9 @@ struct Path {
 // means the step ran away: the path becomes NaN and is counted as non-finite.
 template <typename R>
 __device__ __forceinline__ void fold(Path<R>& p, R H) {
-    if (p.x < (R)0 || p.x > H) {
+    if (__builtin_expect(p.x < (R)0 || p.x > H, 0)) {
         int count = 0;
+#pragma unroll 1
         do {
             if (++count > kFoldMax) {
                 p.x = (R)NAN;

@@ -28,6 +28,8 @@ int smoothing_coefficients(int r, double* coef);
 
 // Launch plan of one (level, range): samples per lane and block count.
 void plan_item(uint64_t n_samples, uint32_t* spl, uint32_t* n_blocks);
+// Upper bound of the blocks any level's range of n_samples uses (either block mode).
+uint32_t max_blocks(uint64_t n_samples);
 
 // Builds the items of a batch (most expensive level first), returns total blocks.
 int build_batch(const ld_problem* p, ld_integrator integ, ld_precision prec,

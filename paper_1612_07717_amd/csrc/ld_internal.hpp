@@ -18,6 +18,15 @@ constexpr int kBlock = 256;       // threads per block of the level kernel (4 wa
 constexpr int kMaxItems = 40;     // (level, range) items per launch
 constexpr int kMaxCoef = 10;      // smoothing polynomial p_r, r <= 8
 
+// Block modes. STREAM: each lane runs whole coupled samples (throughput). PIPE: a block
+// serves 64 samples with its four waves specialised - two draw normals, one advances
+// the fine paths, one the coarse paths - handing data through LDS, so the per-sample
+// instruction stream of the critical (fine) wave is short (latency of long paths).
+enum { KMODE_STREAM = 0, KMODE_PIPE = 1 };
+constexpr int kPipeChunk = 8;                     // coarse steps per LDS hand-off
+constexpr uint64_t kPipeMaxSamples = 64u * 2048u; // larger ranges fill the GPU in STREAM mode
+constexpr uint32_t kPipeMinSteps = 256;           // shorter paths are not latency-critical
+
 // Problem parameters in FP64, prepared on the host (kernel argument).
 struct KProblem {
     double H, eps_reg, ks, kappa_tau, sigma_u, tau, T;
@@ -33,13 +42,14 @@ struct KProblem {
 // cover it; each lane of a block handles `spl` samples.
 struct KItem {
     int32_t level;
-    uint32_t spl;
+    uint32_t spl;           // samples per lane (STREAM mode)
     uint32_t block_begin;
     uint32_t n_blocks;
     uint64_t sample_begin;
     uint64_t n_samples;
     uint32_t out_slot;
-    uint32_t pad;
+    uint16_t mode;          // KMODE_*
+    uint16_t prio;          // wave priority 0..3 (longest paths highest)
 };
 
 struct KArgs {

@@ -1,0 +1,107 @@
+"""GPU tests of the block modes and of the full-size workloads.
+
+- A level range small enough for the wave-specialised (PIPE) blocks and the same range
+  extended past that size (STREAM blocks) give bitwise identical per-sample results:
+  both modes run the same arithmetic on the same draws.
+- Full size: the single large estimate (neutral layer, BAOAB, dt_0 = T/8, levels
+  0..12, relative eps 1e-4) in the launch configuration the benchmark times; sampled
+  outputs are recomputed one by one by the oracle.
+- The well-mixed test with 10^6 particles (uniform on [0, H] stays uniform) and the
+  homogeneous closed forms at 10^6 samples per level.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle
+import paper_1612_07717_amd as ld
+import workloads as W
+from test_oracle_closed_forms import _level_law, fold_mean
+
+pytestmark = pytest.mark.gpu
+
+PIPE_MAX = 64 * 2048
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.mark.parametrize("integ,prec", [("BAOAB", "fp32"), ("GL", "fp64"), ("SE", "fp32"), ("BAOAB", "fp64")])
+def test_pipe_and_stream_blocks_agree_bitwise(integ, prec):
+    cfg = W.neutral(400.0, integ)          # M_0 = 40: level 3 has 320 fine steps
+    say(f"case modes {integ} {prec}")
+    pipe = ld.level_samples(cfg, 3, 11, PIPE_MAX, prec)        # PIPE blocks
+    stream = ld.level_samples(cfg, 3, 11, PIPE_MAX + 1, prec)  # STREAM blocks
+    assert np.array_equal(pipe, stream[:PIPE_MAX])
+    s_pipe = ld.level_sums(cfg, 3, 11, 777, prec)
+    ref = stream[:777]
+    y = ref[:, 0] - ref[:, 1]
+    assert s_pipe["n"] == 777
+    assert abs(s_pipe["sum_y"] - y.sum()) <= 1e-12 * np.abs(y).sum()
+
+
+def _sampled_parity(cfg, level, n, prec, k=48, seed=0):
+    """Run the whole range on the GPU, recompute k sampled outputs with the oracle."""
+    got = ld.level_samples(cfg, level, 0, n, prec)
+    idx = np.unique(np.concatenate([[0, n - 1], np.random.default_rng(seed).integers(0, n, k)]))
+    ref = np.array([oracle.sample(cfg, level, int(i))[:2] for i in idx])
+    return got[idx], ref
+
+
+def test_full_size_sampled_parity_fp64():
+    """The per-level sample counts of the large single estimate, FP64 paths: every
+    sampled output within 1e-12 of the oracle's."""
+    cfg = W.single_large("BAOAB")
+    sizes = [(0, 19_713_142), (1, 574_618), (4, 25_751), (8, 10_000), (12, 10_000)]
+    for level, n in sizes:
+        say(f"case full-size fp64 level={level} n={n}")
+        got, ref = _sampled_parity(cfg, level, n, "fp64", k=24 if level < 8 else 6)
+        tol = 1e-12 * np.maximum(np.abs(ref), 1.0)
+        assert np.all(np.abs(got - ref) <= tol), (level, np.abs(got - ref).max())
+
+
+def test_full_size_fp32_error_statement():
+    """FP32 paths against the FP64 oracle on the same draws at the benchmark sizes:
+    the per-sample position error stays at the FP32 rounding level in distribution."""
+    cfg = W.single_large("BAOAB")
+    for level, n in [(0, 19_713_142), (3, 72_168), (12, 10_000)]:
+        say(f"case full-size fp32 level={level} n={n}")
+        got, ref = _sampled_parity(cfg, level, n, "fp32", k=40 if level < 8 else 8)
+        err = np.abs(got - ref)
+        say(f"  fp32 |err| median {np.median(err):.3e} max {err.max():.3e} m")
+        assert np.median(err) < 0.05 and np.quantile(err, 0.9) < 1.0
+
+
+def test_well_mixed_one_million_particles():
+    """Sec. 2 well-mixed condition: 10^6 particles uniform on [0, H] with the conditional
+    Gaussian velocity remain uniform at T (20 bins of 50 m), BAOAB, FP64 and FP32."""
+    for prec in ("fp64", "fp32"):
+        cfg = W.well_mixed("BAOAB", M0=160)
+        x = ld.level_samples(cfg, 0, 0, 1_000_000, prec)[:, 0]
+        counts, _ = np.histogram(x, bins=20, range=(0.0, 1000.0))
+        chi2 = stats.chisquare(counts)
+        say(f"well-mixed {prec}: chi2 {chi2.statistic:.1f} p {chi2.pvalue:.3g} "
+            f"max dev {np.abs(counts / 50000 - 1).max():.4f}")
+        assert chi2.pvalue > 1e-3
+
+
+@pytest.mark.parametrize("integ", ["SE", "GL", "BAOAB"])
+def test_homogeneous_closed_form_at_scale(integ):
+    """10^6 samples per level: mean of the fine and coarse positions against the exact
+    folded-Gaussian means of the per-level laws (release at 100 m, w0 = 0)."""
+    cfg = W.homogeneous(integrator=integ, release="fixed", z0=100.0, w0=0.0)
+    n = 1_000_000
+    for level in (0, 2, 4):
+        s = ld.level_samples(cfg, level, 0, n, "fp64")
+        for col, lev in ((0, level), (1, level - 1)):
+            if lev < 0:
+                continue
+            m, Cv = _level_law(cfg, integ, lev)
+            exact = fold_mean(m[1], math.sqrt(Cv[1, 1]))
+            x = s[:, col]
+            assert abs(x.mean() - exact) < 4.5 * x.std() / math.sqrt(n), (level, lev, x.mean(), exact)
