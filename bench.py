@@ -132,12 +132,23 @@ def main():
 
     fine_steps = sum(r["fine_steps"] for r in results)
     value = fine_steps / elapsed
+
+    # The same estimate with all-FP64 paths (time-to-eps), and the FP32 run's error
+    # against FP64 paths on identical draws and sample counts.
+    last = results[-1]
+    other = "fp64" if args.precision == "fp32" else "fp32"
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    r_other = ld.estimate(eps, cfg, **dict(kw, precision=other))
+    torch.cuda.synchronize()
+    t_other = time.perf_counter() - t1
+    same = ld.level_sums_batch(cfg, [(l, 0, n) for l, n in enumerate(last["N"])], other)
+    est_other_same_n = sum(s["sum_y"] / s["n"] for s in same)
     dev_s = sum(r["device_seconds"] for r in results)
     launches = sum(r["launches"] for r in results)
     ops = OPS_PER_COUPLED_STEP[(args.integrator, cfg["profile"])]
     achieved = ops * fine_steps / dev_s / 1e12
     peak = PEAK_TFLOPS[args.precision]
-    last = results[-1]
     line = {
         "metric": "coupled particle-steps/s",
         "value": value,
@@ -158,7 +169,10 @@ def main():
                    "levels": L + 1, "N_l": last["N"], "fine_steps_per_step": last["fine_steps"],
                    "estimate_m": last["estimate"], "rmse_est_m": last["rmse_est"],
                    "time_to_eps_s": last["wall_seconds"], "kernel_s_per_step": dev_s / args.steps,
-                   "launches_per_step": launches / args.steps},
+                   "launches_per_step": launches / args.steps,
+                   f"time_to_eps_{other}_s": t_other,
+                   f"estimate_{other}_m": r_other["estimate"],
+                   f"{args.precision}_minus_{other}_same_draws_m": last["estimate"] - est_other_same_n},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": hbm_traffic(args.precision),
                      "kernel": f"level_kernel<{'float' if args.precision == 'fp32' else 'double'}>",

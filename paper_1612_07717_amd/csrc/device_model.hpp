@@ -49,6 +49,17 @@ struct Math<float> {
     static __device__ __forceinline__ float clamp_(float x, float lo, float hi) {
         return __builtin_amdgcn_fmed3f(x, lo, hi);
     }
+    // sqrt(d) and 1/d from one reciprocal square root
+    static __device__ __forceinline__ void sqrt_and_rcp(float d, float& sq, float& inv) {
+        const float r = __builtin_amdgcn_rsqf(d);
+        sq = d * r;
+        inv = r * r;
+    }
+    // x < 0 or x > H (H > 0): non-negative floats order as their bit patterns, and a
+    // set sign bit (or a NaN) compares above H's pattern
+    static __device__ __forceinline__ bool outside(float x, float H) {
+        return __float_as_uint(x) > __float_as_uint(H);
+    }
     // expm1 by argument reduction x = k ln2 + r, |r| <= ln2/2 (Cody & Waite's two-part
     // ln2), the Taylor series of expm1(r) to degree 7 (truncation < 2e-8 relative), and
     // expm1(x) = 2^k expm1(r) + (2^k - 1), which has no cancellation for k != 0.
@@ -82,14 +93,21 @@ struct Math<double> {
     static __device__ __forceinline__ double clamp_(double x, double lo, double hi) {
         return fmin(fmax(x, lo), hi);
     }
+    static __device__ __forceinline__ void sqrt_and_rcp(double d, double& sq, double& inv) {
+        sq = sqrt(d);
+        inv = 1.0 / d;
+    }
+    static __device__ __forceinline__ bool outside(double x, double H) { return x < 0.0 || x > H; }
 };
 
 // Per-(problem, level) constants in the path precision.
 template <typename R>
 struct Consts {
     R H, invH, eps, Hme;        // domain and cut-off heights
+    R sqrt_invH;                // H^(-1/2)
     R ks;                       // kappa_sigma u_*
     R acoef;                    // (3/4) (kappa_sigma u_*)^2 / H
+    R acoef_h;                  // (3/4) (kappa_sigma u_*)^2 / H^(3/2)
     R inv_kt;                   // 1 / kappa_tau
     R su_h, lam_h;              // homogeneous sigma_U and lambda
 };
@@ -99,10 +117,12 @@ __device__ __forceinline__ Consts<R> make_consts(const KProblem& p) {
     Consts<R> c;
     c.H = (R)p.H;
     c.invH = (R)(1.0 / p.H);
+    c.sqrt_invH = (R)(1.0 / sqrt(p.H));
     c.eps = (R)p.eps_reg;
     c.Hme = (R)(p.H - p.eps_reg);
     c.ks = (R)p.ks;
     c.acoef = (R)(0.75 * p.ks * p.ks / p.H);
+    c.acoef_h = (R)(0.75 * p.ks * p.ks / (p.H * sqrt(p.H)));
     c.inv_kt = (R)(1.0 / p.kappa_tau);
     c.su_h = (R)p.sigma_u;
     c.lam_h = (R)(1.0 / p.tau);
@@ -134,16 +154,21 @@ __device__ __forceinline__ void coeffs_at(const Consts<R>& c, R x, R& su, R& lam
         b = (R)0;
     } else {
         const R xc = Math<R>::clamp_(x, c.eps, c.Hme);
-        const R s = (c.H - xc) * c.invH;
-        const R sq = Math<R>::sqrt_(s);
+        const R d = c.H - xc;
+        R sqd, invd;
+        Math<R>::sqrt_and_rcp(d, sqd, invd);
+        const R s = d * c.invH;
+        const R sq = sqd * c.sqrt_invH;                     // sqrt(1 - X/H)
         su = c.ks * Math<R>::sqrt_(s * sq);
         lam = su * c.inv_kt * Math<R>::rcp(xc);
         const bool inside = (x >= c.eps) && (x <= c.Hme);   // then xc == x
-        a = inside ? c.acoef * sq : (R)0;
-        b = inside ? (R)0.75 * Math<R>::rcp(c.H - x) : (R)0;
+        a = inside ? c.acoef_h * sqd : (R)0;
+        b = inside ? (R)0.75 * invd : (R)0;
     }
 }
 
+// a = (3/4)(kappa_sigma u_*)^2 sqrt(H - X) / H^(3/2), b = (3/4) / (H - X) inside
+// [eps_reg, H - eps_reg], 0 outside.
 template <typename R, int PROF>
 __device__ __forceinline__ void drift_at(const Consts<R>& c, R x, R& a, R& b) {
     if (PROF == KPROFILE_HOMOGENEOUS) {
@@ -151,9 +176,10 @@ __device__ __forceinline__ void drift_at(const Consts<R>& c, R x, R& a, R& b) {
         b = (R)0;
     } else {
         const bool inside = (x >= c.eps) && (x <= c.Hme);
-        const R s = (c.H - x) * c.invH;
-        a = inside ? c.acoef * Math<R>::sqrt_(s) : (R)0;
-        b = inside ? (R)0.75 * Math<R>::rcp(c.H - x) : (R)0;
+        R sq, inv;
+        Math<R>::sqrt_and_rcp(c.H - x, sq, inv);
+        a = inside ? c.acoef_h * sq : (R)0;
+        b = inside ? (R)0.75 * inv : (R)0;
     }
 }
 
@@ -169,7 +195,7 @@ struct Path {
 // means the step ran away: the path becomes NaN and is counted as non-finite.
 template <typename R>
 __device__ __forceinline__ void fold(Path<R>& p, R H) {
-    if (__builtin_expect(p.x < (R)0 || p.x > H, 0)) {
+    if (__builtin_expect(Math<R>::outside(p.x, H), 0)) {
         int count = 0;
 #pragma unroll 1
         do {
