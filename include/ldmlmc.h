@@ -245,6 +245,83 @@ int mlmc_estimate(double eps, const ld_qoi* qoi, ld_integrator integrator,
                   const ld_profile* profile, const ld_estimate_opts* opts,
                   ld_estimate_result* out);
 
+/* ---- many estimators at once: the engine ---------------------------------------- */
+
+/* The engine runs many independent MLMC estimates (queries) together. Each iteration
+   gathers every active query's planned (level, sample range) pairs, cuts them into
+   tiles (one block's work: 256 lanes x spl samples, or 64 samples in wave-specialised
+   blocks for long paths), and runs all tiles of all queries in one persistent kernel
+   per turbulence profile that takes tiles from a queue; the longest paths go first.
+   The tile partials are reduced per range in a fixed order and added to running sums
+   that stay in device memory (one ld_level_sums per query slot and level). After each
+   iteration every query's planner (mlmc_plan) decides its next samples. A query's
+   tiles and sums depend only on the query itself, so its result is bitwise the same
+   run alone or mixed with others. Queries are admitted while slots and the HBM budget
+   allow (LD_EBUSY otherwise), and leave when converged: continuous batching. */
+
+#define LD_PENDING 2             /* ld_engine_result: the query is still running        */
+#define LD_EBUSY (-7)            /* ld_engine_submit: no free slot within the HBM budget */
+
+typedef struct ld_engine ld_engine;   /* opaque */
+
+typedef struct {
+    ld_precision precision;       /* path arithmetic of all queries */
+    int32_t max_queries;          /* query slots (default 256) */
+    size_t hbm_budget_bytes;      /* device memory the engine may use (default 1 GiB) */
+    int32_t blocks_per_cu;        /* persistent grid = blocks_per_cu x CUs (default 8) */
+    uint64_t target_tiles;        /* STREAM ranges are cut into at most this many tiles
+                                     before lanes take several samples (default 32768) */
+    uint64_t pipe_max_samples;    /* wave-specialised tiles for ranges up to this size
+                                     (default 131072; 0 disables them) */
+    uint32_t pipe_min_steps;      /* ... whose paths have at least this many steps (256) */
+    int32_t use_graph;            /* capture an iteration's launches in a hipGraph (1) */
+    void* hip_stream;             /* stream of all engine work (NULL = default) */
+} ld_engine_opts;
+
+/* One estimation request: mlmc_estimate's arguments. */
+typedef struct {
+    ld_problem problem;
+    ld_integrator integrator;
+    int32_t eps_is_relative;
+    double eps;
+    int32_t L_min, L_max, fixed_L, max_iter;
+    uint64_t N_init;
+    double alpha;
+} ld_query;
+
+void ld_engine_default_opts(ld_engine_opts* opts);
+/* Allocates the engine's device buffers (within hbm_budget_bytes) on the current
+   device. LD_EINVAL for bad options, LD_ENOMEM if the budget cannot hold one query. */
+int ld_engine_create(const ld_engine_opts* opts, ld_engine** out);
+void ld_engine_destroy(ld_engine* engine);
+/* Admits a query (validated as mlmc_estimate would). *handle identifies it until
+   ld_engine_release. LD_EBUSY: no free slot now; retry after queries finish. */
+int ld_engine_submit(ld_engine* engine, const ld_query* query, int64_t* handle);
+/* One MLMC iteration of every active query (blocks until its results are back).
+   *n_active receives the number of queries still running afterwards. */
+int ld_engine_step(ld_engine* engine, int32_t* n_active);
+/* LD_PENDING while running; otherwise the query's final status (as mlmc_estimate) with
+   out filled. wall_seconds = time from submission to completion. */
+int ld_engine_result(ld_engine* engine, int64_t handle, ld_estimate_result* out);
+/* Frees a finished query's slot. */
+int ld_engine_release(ld_engine* engine, int64_t handle);
+/* Device seconds of all iterations so far (HIP events), and their count. */
+int ld_engine_stats(ld_engine* engine, double* device_seconds, int64_t* iterations,
+                    double* fine_steps);
+
+/* Runs n queries to completion on one engine (submitting as slots free up) and fills
+   out[0..n-1]. Returns the worst status. */
+int mlmc_estimate_batch(const ld_query* queries, int32_t n, const ld_engine_opts* opts,
+                        ld_estimate_result* out);
+
+/* Autotuner: times the batch `queries` on engines with each candidate persistent grid
+   (blocks_per_cu in {2, 4, 6, 8, 12, 16}) and tile policy (target_tiles in
+   {4096, 8192, 16384, 32768, 65536}, wave-specialised tiles on/off), keeps the
+   fastest, and writes it to *best (other fields from base). reps timings per
+   candidate, the median counts. */
+int ld_engine_autotune(const ld_query* queries, int32_t n, const ld_engine_opts* base,
+                       int32_t reps, ld_engine_opts* best, double* best_seconds);
+
 /* ---- errors --------------------------------------------------------------------- */
 const char* ld_strerror(int status);
 /* Message of the last error on the calling thread ("" if none). */

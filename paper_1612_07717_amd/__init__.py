@@ -28,7 +28,11 @@ QOIS = {"mean_z": 0, "p_above": 1, "p_box": 2, "velocity": 3, "velocity_sq": 4}
 EXPORTED = ["mlmc_level_sums_workspace", "mlmc_level_sums", "mlmc_level_sums_batch_workspace",
             "mlmc_level_sums_batch", "mlmc_level_samples", "mlmc_plan",
             "mlmc_estimate_default_opts", "mlmc_estimate_workspace", "mlmc_estimate",
+            "ld_engine_default_opts", "ld_engine_create", "ld_engine_destroy", "ld_engine_submit",
+            "ld_engine_step", "ld_engine_result", "ld_engine_release", "ld_engine_stats",
+            "mlmc_estimate_batch", "ld_engine_autotune",
             "ld_strerror", "ld_last_error"]
+LD_PENDING, LD_EBUSY = 2, -7
 
 
 class LdError(RuntimeError):
@@ -105,6 +109,21 @@ class EstimateResult(C.Structure):
                 ("reserved2", C.c_int32)]
 
 
+class EngineOpts(C.Structure):
+    _fields_ = [("precision", C.c_int32), ("max_queries", C.c_int32),
+                ("hbm_budget_bytes", C.c_size_t), ("blocks_per_cu", C.c_int32),
+                ("target_tiles", C.c_uint64), ("pipe_max_samples", C.c_uint64),
+                ("pipe_min_steps", C.c_uint32), ("use_graph", C.c_int32),
+                ("hip_stream", C.c_void_p)]
+
+
+class Query(C.Structure):
+    _fields_ = [("problem", Problem), ("integrator", C.c_int32), ("eps_is_relative", C.c_int32),
+                ("eps", C.c_double), ("L_min", C.c_int32), ("L_max", C.c_int32),
+                ("fixed_L", C.c_int32), ("max_iter", C.c_int32), ("N_init", C.c_uint64),
+                ("alpha", C.c_double)]
+
+
 _lib = None
 
 
@@ -137,6 +156,19 @@ def load():
     lib.ld_strerror.argtypes = [C.c_int]
     lib.ld_strerror.restype = C.c_char_p
     lib.ld_last_error.restype = C.c_char_p
+    lib.ld_engine_default_opts.argtypes = [P(EngineOpts)]
+    lib.ld_engine_default_opts.restype = None
+    lib.ld_engine_create.argtypes = [P(EngineOpts), P(C.c_void_p)]
+    lib.ld_engine_destroy.argtypes = [C.c_void_p]
+    lib.ld_engine_destroy.restype = None
+    lib.ld_engine_submit.argtypes = [C.c_void_p, P(Query), P(C.c_int64)]
+    lib.ld_engine_step.argtypes = [C.c_void_p, P(C.c_int32)]
+    lib.ld_engine_result.argtypes = [C.c_void_p, C.c_int64, P(EstimateResult)]
+    lib.ld_engine_release.argtypes = [C.c_void_p, C.c_int64]
+    lib.ld_engine_stats.argtypes = [C.c_void_p, P(C.c_double), P(C.c_int64), P(C.c_double)]
+    lib.mlmc_estimate_batch.argtypes = [P(Query), C.c_int32, P(EngineOpts), P(EstimateResult)]
+    lib.ld_engine_autotune.argtypes = [P(Query), C.c_int32, P(EngineOpts), C.c_int32,
+                                       P(EngineOpts), P(C.c_double)]
     _lib = lib
     return lib
 
@@ -331,3 +363,133 @@ def plan(d: dict) -> dict:
             "Yhat": list(out.Yhat[: d["L"] + 1]), "V": list(out.V[: d["L"] + 1]),
             "estimate": out.estimate, "eps_abs": out.eps_abs, "alpha": out.alpha,
             "bias_est": out.bias_est, "stat_var": out.stat_var}
+
+
+# ------------------------------------------------------------------------- the engine
+def _result_dict(r: EstimateResult, rc: int) -> dict:
+    L = r.L
+    return {"rc": rc, "estimate": r.estimate, "eps_abs": r.eps_abs, "bias_est": r.bias_est,
+            "stat_var": r.stat_var, "rmse_est": r.rmse_est, "alpha": r.alpha, "L": L,
+            "iterations": r.iterations, "status": r.status,
+            "N": [int(r.N[l]) for l in range(L + 1)], "n_nonfinite": int(r.n_nonfinite),
+            "Yhat": list(r.Yhat[: L + 1]), "V": list(r.V[: L + 1]),
+            "fine_steps": r.fine_steps, "integrator_steps": r.integrator_steps,
+            "wall_seconds": r.wall_seconds, "device_seconds": r.device_seconds,
+            "launches": r.launches}
+
+
+def make_query(cfg: dict, eps: float, *, eps_is_relative=True, L_min=2, L_max=20, fixed_L=-1,
+               N_init=10000, alpha=1.0, max_iter=100) -> Query:
+    return Query(problem=make_problem(cfg), integrator=INTEGRATORS[cfg["integrator"]],
+                 eps_is_relative=int(bool(eps_is_relative)), eps=float(eps), L_min=L_min,
+                 L_max=L_max, fixed_L=fixed_L, max_iter=max_iter, N_init=int(N_init),
+                 alpha=float(alpha))
+
+
+def engine_opts(*, precision="fp32", max_queries=256, hbm_budget_bytes=1 << 30, blocks_per_cu=8,
+                target_tiles=32768, pipe_max_samples=64 * 2048, pipe_min_steps=256,
+                use_graph=True, stream=None) -> EngineOpts:
+    o = EngineOpts()
+    load().ld_engine_default_opts(C.byref(o))
+    o.precision = PRECISIONS[precision]
+    o.max_queries = int(max_queries)
+    o.hbm_budget_bytes = int(hbm_budget_bytes)
+    o.blocks_per_cu = int(blocks_per_cu)
+    o.target_tiles = int(target_tiles)
+    o.pipe_max_samples = int(pipe_max_samples)
+    o.pipe_min_steps = int(pipe_min_steps)
+    o.use_graph = int(bool(use_graph))
+    if stream is not None:
+        o.hip_stream = _stream_handle(stream).value
+    return o
+
+
+class Engine:
+    """ld_engine: submit queries, step MLMC iterations of all of them, read results."""
+
+    def __init__(self, opts: EngineOpts | None = None, **kw):
+        _torch()
+        self._lib = load()
+        self._opts = opts if opts is not None else engine_opts(**kw)
+        h = C.c_void_p()
+        _check(self._lib.ld_engine_create(C.byref(self._opts), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if self._h:
+            self._lib.ld_engine_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, query: Query):
+        """Handle of the admitted query, or None if no slot is free (LD_EBUSY)."""
+        h = C.c_int64()
+        rc = self._lib.ld_engine_submit(self._h, C.byref(query), C.byref(h))
+        if rc == LD_EBUSY:
+            return None
+        _check(rc)
+        return int(h.value)
+
+    def step(self) -> int:
+        n = C.c_int32()
+        _check(self._lib.ld_engine_step(self._h, C.byref(n)))
+        return int(n.value)
+
+    def result(self, handle: int):
+        """Result dict once finished, None while pending."""
+        r = EstimateResult()
+        rc = self._lib.ld_engine_result(self._h, int(handle), C.byref(r))
+        if rc == LD_PENDING:
+            return None
+        _check(rc, ok=(LD_OK, LD_WARN_NOT_CONVERGED, LD_ENONFINITE))
+        return _result_dict(r, rc)
+
+    def release(self, handle: int):
+        _check(self._lib.ld_engine_release(self._h, int(handle)))
+
+    def stats(self) -> dict:
+        d, it, fs = C.c_double(), C.c_int64(), C.c_double()
+        _check(self._lib.ld_engine_stats(self._h, C.byref(d), C.byref(it), C.byref(fs)))
+        return {"device_seconds": d.value, "iterations": int(it.value), "fine_steps": fs.value}
+
+
+def estimate_batch(queries: list, opts: EngineOpts | None = None, **kw) -> list:
+    """mlmc_estimate_batch: all queries to completion on one engine."""
+    _torch()
+    lib = load()
+    o = opts if opts is not None else engine_opts(**kw)
+    arr = (Query * len(queries))(*queries)
+    res = (EstimateResult * len(queries))()
+    rc = lib.mlmc_estimate_batch(arr, len(queries), C.byref(o), res)
+    _check(rc, ok=(LD_OK, LD_WARN_NOT_CONVERGED, LD_ENONFINITE))
+    return [_result_dict(r, r.status) for r in res]
+
+
+def autotune(queries: list, base: EngineOpts | None = None, reps: int = 2, **kw):
+    """ld_engine_autotune: the fastest engine options for this batch, and its time."""
+    _torch()
+    lib = load()
+    b = base if base is not None else engine_opts(**kw)
+    arr = (Query * len(queries))(*queries)
+    best = EngineOpts()
+    t = C.c_double()
+    _check(lib.ld_engine_autotune(arr, len(queries), C.byref(b), int(reps), C.byref(best), C.byref(t)))
+    return best, t.value
+
+
+def opts_dict(o: EngineOpts) -> dict:
+    return {"precision": "fp32" if o.precision == 1 else "fp64", "max_queries": o.max_queries,
+            "hbm_budget_bytes": o.hbm_budget_bytes, "blocks_per_cu": o.blocks_per_cu,
+            "target_tiles": o.target_tiles, "pipe_max_samples": o.pipe_max_samples,
+            "pipe_min_steps": o.pipe_min_steps, "use_graph": bool(o.use_graph)}

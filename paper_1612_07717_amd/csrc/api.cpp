@@ -285,6 +285,8 @@ const char* ld_strerror(int status) {
         case LD_EDEVICE: return "HIP device error";
         case LD_ENONFINITE: return "non-finite samples";
         case LD_ENODEVICE: return "no usable device";
+        case LD_PENDING: return "query still running";
+        case LD_EBUSY: return "no free query slot within the HBM budget";
         default: return "unknown status";
     }
 }

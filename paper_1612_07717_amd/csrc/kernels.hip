@@ -86,6 +86,56 @@ __device__ __forceinline__ void block_reduce(Acc& a) {
     }
 }
 
+// Wave index as a scalar (uniform) value: branches on it are scalar branches.
+__device__ __forceinline__ uint32_t wave_index() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+// Block reduction for loops that take work item by item (persistent and grid-stride
+// kernels): like block_reduce, but every thread ends with the block total (the wave
+// results are merged in the same fixed order by all threads), so no single-lane
+// region sits at the end of a loop body. Ends with a barrier: LDS may be reused.
+__device__ __forceinline__ void block_reduce_all(Acc& a) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const double so = __shfl_xor(a.s[k], off, 64);
+            const double co = __shfl_xor(a.c[k], off, 64);
+            neumaier_merge(a.s[k], a.c[k], so, co);
+        }
+        a.n += __shfl_xor(a.n, off, 64);
+        a.nbad += __shfl_xor(a.nbad, off, 64);
+    }
+    constexpr int kWaves = kBlock / 64;
+    __shared__ double sh_s[kWaves][4], sh_c[kWaves][4];
+    __shared__ uint64_t sh_n[kWaves], sh_bad[kWaves];
+    const uint32_t wave = wave_index();
+    // every lane of a wave holds the wave total; all of them store the same values
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        sh_s[wave][k] = a.s[k];
+        sh_c[wave][k] = a.c[k];
+    }
+    sh_n[wave] = a.n;
+    sh_bad[wave] = a.nbad;
+    __syncthreads();
+    Acc t;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        t.s[k] = sh_s[0][k];
+        t.c[k] = sh_c[0][k];
+    }
+    t.n = sh_n[0];
+    t.nbad = sh_bad[0];
+    for (int w = 1; w < kWaves; ++w) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) neumaier_merge(t.s[k], t.c[k], sh_s[w][k], sh_c[w][k]);
+        t.n += sh_n[w];
+        t.nbad += sh_bad[w];
+    }
+    a = t;
+    __syncthreads();
+}
+
 __device__ __forceinline__ void store_sums(ld_level_sums* out, const Acc& a) {
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -141,7 +191,7 @@ __device__ __forceinline__ void pipe_samples(const KProblem& kp, const Consts<R>
     auto& msg = L.msg;
     auto& end_pc = L.end_pc;
     auto& end_bad = L.end_bad;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = (int)wave_index(), lane = threadIdx.x & 63;   // roles: scalar branches
     const uint64_t local = (uint64_t)local_block * 64 + lane;
     const bool active = local < item.n_samples;
     const int level = item.level;
@@ -232,30 +282,21 @@ __device__ __forceinline__ void set_priority(uint32_t prio) {
         case 3: __builtin_amdgcn_s_setprio(3); break;
         case 2: __builtin_amdgcn_s_setprio(2); break;
         case 1: __builtin_amdgcn_s_setprio(1); break;
-        default: break;
+        default: __builtin_amdgcn_s_setprio(0); break;
     }
 }
 
-// One kernel per (path precision, integrator, profile): all items of a launch share the
-// problem, so the choice is made on the host and each kernel holds two path bodies only.
+// The work of one block: block `local_block` of `item`, in the item's mode. acc receives
+// this block's sums (valid in thread 0 after block_reduce).
 template <typename R, int INTEG, int PROF>
-__global__ __launch_bounds__(kBlock) void level_kernel(const KArgs args,
-                                                       ld_level_sums* __restrict__ partials,
-                                                       double* __restrict__ dump) {
-    const uint32_t b = blockIdx.x;
-    int it = 0;
-    while (it + 1 < args.n_items && b >= args.items[it].block_begin + args.items[it].n_blocks) ++it;
-    const KItem item = args.items[it];
-    const KProblem& kp = args.prob;
+__device__ __forceinline__ void run_block(const KProblem& kp, const KItem& item,
+                                          uint32_t local_block, Acc& acc, double* dump,
+                                          PipeLds<R>& lds) {
     const Consts<R> c = make_consts<R>(kp);
-    set_priority(item.prio);
-    Acc acc;
-    acc_zero(acc);
     if (item.mode == KMODE_PIPE) {
-        __shared__ PipeLds<R> lds;
-        pipe_samples<R, INTEG, PROF>(kp, c, item, b - item.block_begin, acc, dump, lds);
+        pipe_samples<R, INTEG, PROF>(kp, c, item, local_block, acc, dump, lds);
     } else {
-        const uint64_t base = (uint64_t)(b - item.block_begin) * (uint64_t)kBlock * item.spl;
+        const uint64_t base = (uint64_t)local_block * (uint64_t)kBlock * item.spl;
         for (uint32_t k = 0; k < item.spl; ++k) {
             const uint64_t local = base + (uint64_t)k * kBlock + threadIdx.x;
             if (local < item.n_samples) {
@@ -270,8 +311,136 @@ __global__ __launch_bounds__(kBlock) void level_kernel(const KArgs args,
             }
         }
     }
+}
+
+// One kernel per (path precision, integrator, profile): all items of a launch share the
+// problem, so the choice is made on the host and each kernel holds two path bodies only.
+template <typename R, int INTEG, int PROF>
+__global__ __launch_bounds__(kBlock) void level_kernel(const KArgs args,
+                                                       ld_level_sums* __restrict__ partials,
+                                                       double* __restrict__ dump) {
+    const uint32_t b = blockIdx.x;
+    int it = 0;
+    while (it + 1 < args.n_items && b >= args.items[it].block_begin + args.items[it].n_blocks) ++it;
+    const KItem item = args.items[it];
+    set_priority(item.prio);
+    Acc acc;
+    acc_zero(acc);
+    __shared__ PipeLds<R> lds;
+    run_block<R, INTEG, PROF>(args.prob, item, b - item.block_begin, acc, dump, lds);
     block_reduce(acc);
     if (threadIdx.x == 0) store_sums(&partials[b], acc);
+}
+
+// ---------------------------------------------------------------------------------
+// Persistent multi-estimator kernel. Blocks take tiles (one block's work of one
+// (query, level, range)) from a queue until it is empty; each tile writes its own
+// partial, so the result does not depend on which block ran which tile. Integrators
+// are chosen per tile (uniform per block); the profile is a template parameter.
+// ---------------------------------------------------------------------------------
+template <typename R, int PROF>
+__global__ __launch_bounds__(kBlock) void persistent_kernel(const KHeader* __restrict__ hdr,
+                                                            const KTile* __restrict__ tiles,
+                                                            const KProblem* __restrict__ problems,
+                                                            ld_level_sums* __restrict__ partials,
+                                                            uint32_t* __restrict__ counters) {
+    __shared__ uint32_t sh_tile;
+    __shared__ PipeLds<R> lds;
+    const KQueue q = hdr->queue[PROF];
+    const uint32_t wave = wave_index();
+    const uint32_t lane = threadIdx.x & 63u;
+    // The loop boundary holds no single-lane region (a divergent region there can be
+    // turned into a loop exit for that lane alone, re-running the body for the other
+    // lanes without fetching a new tile): wave 0 fetches the tile under a scalar
+    // branch, every lane issuing the atomic with only lane 0 adding 1.
+    for (;;) {
+        if (wave == 0) {
+            const uint32_t old = atomicAdd(&counters[q.counter], lane == 0 ? 1u : 0u);
+            sh_tile = __builtin_amdgcn_readfirstlane(old);
+        }
+        __syncthreads();
+        const uint32_t t = __builtin_amdgcn_readfirstlane(sh_tile);
+        __syncthreads();
+        if (t >= q.n_tiles) break;
+        const KTile tile = tiles[q.first + t];
+        const KProblem& kp = problems[tile.slot];
+        KItem item;
+        item.level = tile.level;
+        item.spl = tile.spl;
+        item.block_begin = 0;
+        item.n_blocks = 0;
+        item.sample_begin = tile.sample_begin;
+        item.n_samples = tile.n_samples;
+        item.out_slot = 0;
+        item.mode = tile.mode;
+        item.prio = tile.prio;
+        set_priority(tile.prio);
+        Acc acc;
+        acc_zero(acc);
+        switch (kp.integ) {
+            case KINTEG_SE: run_block<R, KINTEG_SE, PROF>(kp, item, tile.local_block, acc, nullptr, lds); break;
+            case KINTEG_GL: run_block<R, KINTEG_GL, PROF>(kp, item, tile.local_block, acc, nullptr, lds); break;
+            default: run_block<R, KINTEG_BAOAB, PROF>(kp, item, tile.local_block, acc, nullptr, lds); break;
+        }
+        block_reduce_all(acc);
+        if (wave == 0) store_sums(&partials[q.first + t], acc);   // same values from every lane
+    }
+}
+
+__global__ void reset_counters_kernel(uint32_t* counters, int n) {
+    if ((int)threadIdx.x < n) counters[threadIdx.x] = 0u;
+}
+
+// Each range's tile partials, in tile order, are reduced and added to the running sums
+// of (query slot, level); also written per range for the caller.
+__global__ __launch_bounds__(kBlock) void merge_ranges_kernel(const KHeader* __restrict__ hdr,
+                                                              const KRange* __restrict__ ranges,
+                                                              const ld_level_sums* __restrict__ partials,
+                                                              ld_level_sums* __restrict__ running,
+                                                              ld_level_sums* __restrict__ range_out) {
+    const uint32_t n_ranges = hdr->n_ranges;
+    for (uint32_t r = blockIdx.x; r < n_ranges; r += gridDim.x) {
+        const KRange rg = ranges[r];
+        Acc acc;
+        acc_zero(acc);
+        for (uint32_t j = threadIdx.x; j < rg.n_tiles; j += kBlock) {
+            const ld_level_sums p = partials[rg.tile_begin + j];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) neumaier_merge(acc.s[k], acc.c[k], p.s[k], p.c[k]);
+            acc.n += p.n;
+            acc.nbad += p.n_nonfinite;
+        }
+        block_reduce_all(acc);
+        if (wave_index() == 0) {   // scalar branch; every lane computes and stores the same values
+            store_sums(&range_out[r], acc);
+            ld_level_sums* run = &running[rg.slot * LD_MAX_LEVELS + rg.level];
+            Acc tot;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                tot.s[k] = run->s[k];
+                tot.c[k] = run->c[k];
+                neumaier_merge(tot.s[k], tot.c[k], acc.s[k], acc.c[k]);
+            }
+            tot.n = run->n + acc.n;
+            tot.nbad = run->n_nonfinite + acc.nbad;
+            store_sums(run, tot);
+        }
+    }
+}
+
+__global__ void clear_sums_kernel(ld_level_sums* sums, uint32_t n) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        ld_level_sums z;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            z.s[k] = 0.0;
+            z.c[k] = 0.0;
+        }
+        z.n = 0;
+        z.n_nonfinite = 0;
+        sums[i] = z;
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void merge_kernel(const KArgs args,
@@ -318,6 +487,35 @@ int launch_levels(const KArgs& args, uint32_t total_blocks, ld_level_sums* d_par
     hipLaunchKernelGGL(merge_kernel, dim3(args.n_items), dim3(kBlock), 0, s, args, d_partials, d_out);
     if (hipGetLastError() != hipSuccess) return LD_EDEVICE;
     return LD_OK;
+}
+
+int launch_engine_iteration(int precision, uint32_t grid_blocks, const KHeader* d_hdr,
+                            const KTile* d_tiles, const KProblem* d_problems,
+                            ld_level_sums* d_partials, uint32_t* d_counters,
+                            const KRange* d_ranges, ld_level_sums* d_running,
+                            ld_level_sums* d_range_out, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, d_counters, 2);
+    if (precision == LD_FP32) {
+        hipLaunchKernelGGL((persistent_kernel<float, KPROFILE_NEUTRAL>), dim3(grid_blocks), dim3(kBlock), 0, s,
+                           d_hdr, d_tiles, d_problems, d_partials, d_counters);
+        hipLaunchKernelGGL((persistent_kernel<float, KPROFILE_HOMOGENEOUS>), dim3(grid_blocks), dim3(kBlock), 0, s,
+                           d_hdr, d_tiles, d_problems, d_partials, d_counters);
+    } else {
+        hipLaunchKernelGGL((persistent_kernel<double, KPROFILE_NEUTRAL>), dim3(grid_blocks), dim3(kBlock), 0, s,
+                           d_hdr, d_tiles, d_problems, d_partials, d_counters);
+        hipLaunchKernelGGL((persistent_kernel<double, KPROFILE_HOMOGENEOUS>), dim3(grid_blocks), dim3(kBlock), 0, s,
+                           d_hdr, d_tiles, d_problems, d_partials, d_counters);
+    }
+    hipLaunchKernelGGL(merge_ranges_kernel, dim3(kMergeGrid), dim3(kBlock), 0, s, d_hdr, d_ranges, d_partials,
+                       d_running, d_range_out);
+    return hipGetLastError() == hipSuccess ? LD_OK : LD_EDEVICE;
+}
+
+int launch_clear_sums(ld_level_sums* d_sums, uint32_t n, void* stream) {
+    if (n == 0) return LD_OK;
+    hipLaunchKernelGGL(clear_sums_kernel, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, d_sums, n);
+    return hipGetLastError() == hipSuccess ? LD_OK : LD_EDEVICE;
 }
 
 }  // namespace ldm

@@ -64,4 +64,51 @@ struct KArgs {
 int launch_levels(const KArgs& args, uint32_t total_blocks, ld_level_sums* d_partials,
                   ld_level_sums* d_out, double* d_dump, void* stream);
 
+// ---- multi-estimator engine ------------------------------------------------------
+// A tile is one block's work: block `local_block` of the range (slot, level,
+// sample_begin, n_samples) in the given mode.
+struct KTile {
+    uint32_t slot;          // query slot: index into the problem table and running sums
+    int32_t level;
+    uint64_t sample_begin;  // first sample of the range
+    uint64_t n_samples;     // samples in the range
+    uint32_t local_block;
+    uint32_t spl;
+    uint16_t mode;
+    uint16_t prio;
+    uint32_t pad;
+};
+
+struct KQueue {
+    uint32_t first;         // first tile of this queue in the tile table
+    uint32_t n_tiles;
+    uint32_t counter;       // index of its counter in the counter array
+    uint32_t pad;
+};
+
+struct KHeader {
+    KQueue queue[2];        // by profile kind
+    uint32_t n_ranges;
+    uint32_t pad[3];
+};
+
+// A range's tiles are contiguous: partials [tile_begin, tile_begin + n_tiles).
+struct KRange {
+    uint32_t slot;
+    int32_t level;
+    uint32_t tile_begin;
+    uint32_t n_tiles;
+};
+
+constexpr int kMergeGrid = 256;   // blocks of the range-merge kernel (grid-stride)
+
+// Enqueues one engine iteration: reset the queue counters, the persistent kernels of
+// both profiles, then the range merge into the running sums.
+int launch_engine_iteration(int precision, uint32_t grid_blocks, const KHeader* d_hdr,
+                            const KTile* d_tiles, const KProblem* d_problems,
+                            ld_level_sums* d_partials, uint32_t* d_counters,
+                            const KRange* d_ranges, ld_level_sums* d_running,
+                            ld_level_sums* d_range_out, void* stream);
+int launch_clear_sums(ld_level_sums* d_sums, uint32_t n, void* stream);
+
 }  // namespace ldm

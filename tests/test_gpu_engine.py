@@ -1,0 +1,112 @@
+"""GPU tests of the multi-estimator engine (persistent tile kernel, graph replay,
+continuous batching).
+
+- A batch of queries gives exactly the estimates of separate mlmc_estimate calls
+  (same tiling rule per range, same compensated merges, same planner decisions).
+- A query's result is bitwise the same alone and mixed with other queries.
+- FP64 engine estimates equal the oracle's adaptive estimates (same N_l).
+- Admission under a small slot budget, release and re-admission; graph replay
+  equals direct launches.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1612_07717_amd as ld
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _mixed_configs(n, seed=3):
+    """Neutral-layer queries of the batched workload, with tolerances loose enough for
+    a quick test."""
+    qs = W.batched_estimators(n, seed=seed, eps_range=(5e-3, 2e-2))
+    return [(q["problem"], q["eps"]) for q in qs]
+
+
+def test_batch_equals_single_estimates():
+    cfgs = _mixed_configs(6)
+    qs = [ld.make_query(c, e, N_init=2000, L_max=10) for c, e in cfgs]
+    batch = ld.estimate_batch(qs, precision="fp32")
+    for (c, e), b in zip(cfgs, batch):
+        s = ld.estimate(e, c, precision="fp32", eps_is_relative=True, N_init=2000, L_max=10)
+        say(f"batch {c['integrator']} z0={c['z0']:.0f} {c['qoi']}: {b['estimate']:.6f} N={b['N']}")
+        assert b["N"] == s["N"] and b["L"] == s["L"]
+        assert b["estimate"] == s["estimate"]
+        assert b["status"] == s["status"] == 1
+
+
+def test_alone_equals_mixed_bitwise():
+    cfgs = _mixed_configs(12, seed=5)
+    q0 = ld.make_query(*cfgs[0], N_init=2000, L_max=10)
+    alone = ld.estimate_batch([q0], precision="fp32")[0]
+    mixed = ld.estimate_batch([ld.make_query(c, e, N_init=2000, L_max=10) for c, e in cfgs],
+                              precision="fp32")[0]
+    assert alone["N"] == mixed["N"]
+    assert alone["estimate"] == mixed["estimate"]
+    assert alone["Yhat"] == mixed["Yhat"] and alone["V"] == mixed["V"]
+
+
+def test_fp64_engine_matches_oracle_driver():
+    cfgs = [(W.neutral(300.0, "GL"), 1e-2), (W.neutral(700.0, "BAOAB"), 1e-2),
+            (W.problem(integrator="SE"), 2e-2),
+            (W.neutral(450.0, "BAOAB", qoi="p_above", qa=400.0, r=4, delta=100.0), 2e-2)]
+    qs = [ld.make_query(c, e, N_init=3000, L_max=9) for c, e in cfgs]
+    res = ld.estimate_batch(qs, precision="fp64")
+    for (c, e), r in zip(cfgs, res):
+        o = oracle.estimate(e, c, eps_is_relative=True, N_init=3000, L_max=9)
+        say(f"fp64 engine {c['integrator']}: {r['estimate']} N={r['N']} oracle {o['estimate']} N={o['N']}")
+        assert r["N"] == o["N"] and r["L"] == o["L"]
+        assert r["estimate"] == pytest.approx(o["estimate"], rel=1e-11, abs=1e-13)
+
+
+def test_admission_release_and_graph_equivalence():
+    cfgs = _mixed_configs(7, seed=9)
+    qs = [ld.make_query(c, e, N_init=2000, L_max=10) for c, e in cfgs]
+    ref = ld.estimate_batch(qs, precision="fp32", use_graph=False)
+    with ld.Engine(precision="fp32", max_queries=3) as eng:
+        handles = [eng.submit(q) for q in qs[:3]]
+        assert all(h is not None for h in handles)
+        assert eng.submit(qs[3]) is None                 # LD_EBUSY: no slot
+        pending = list(range(3, len(qs)))
+        owner = {h: i for i, h in enumerate(handles)}
+        results = {}
+        steps = 0
+        while len(results) < len(qs):
+            eng.step()
+            steps += 1
+            for h, i in list(owner.items()):
+                r = eng.result(h)
+                if r is not None:
+                    results[i] = r
+                    eng.release(h)
+                    del owner[h]
+            while pending:
+                h = eng.submit(qs[pending[0]])
+                if h is None:
+                    break
+                owner[h] = pending.pop(0)
+            assert steps < 500
+        st = eng.stats()
+        assert st["iterations"] == steps and st["device_seconds"] > 0
+    for i, r in results.items():
+        assert r["N"] == ref[i]["N"] and r["estimate"] == ref[i]["estimate"]
+
+
+def test_autotuner_returns_a_valid_configuration():
+    cfgs = _mixed_configs(4, seed=13)
+    qs = [ld.make_query(c, e, N_init=1000, L_max=8) for c, e in cfgs]
+    best, t = ld.autotune(qs, reps=1, precision="fp32")
+    d = ld.opts_dict(best)
+    say(f"autotune best {d} in {t * 1e3:.2f} ms")
+    assert d["blocks_per_cu"] in (2, 4, 6, 8, 12, 16) and t > 0
+    res = ld.estimate_batch(qs, opts=best)
+    assert all(r["status"] == 1 for r in res)

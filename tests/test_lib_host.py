@@ -54,7 +54,8 @@ def test_struct_layouts_match_header(tmp_path):
                "ld_problem": ld.Problem, "ld_level_sums": ld.LevelSums,
                "ld_level_range": ld.LevelRange, "ld_plan_in": ld.PlanIn,
                "ld_plan_out": ld.PlanOut, "ld_estimate_opts": ld.EstimateOpts,
-               "ld_estimate_result": ld.EstimateResult}
+               "ld_estimate_result": ld.EstimateResult, "ld_engine_opts": ld.EngineOpts,
+               "ld_query": ld.Query}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ldmlmc.h"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -159,3 +160,15 @@ def test_strerror_covers_all_codes(lib):
     for code in (0, 1, -1, -2, -3, -4, -5, -6):
         assert lib.ld_strerror(code).decode() != "unknown status"
     assert lib.ld_strerror(-99).decode() == "unknown status"
+
+
+def test_batch_validates_queries_before_device_use(lib):
+    bad = ld.make_query(W.neutral(300.0, "GL", H=-5.0), 1e-2)
+    good = ld.make_query(W.neutral(300.0, "GL"), 1e-2)
+    arr = (ld.Query * 2)(good, bad)
+    res = (ld.EstimateResult * 2)()
+    assert lib.mlmc_estimate_batch(arr, 2, None, res) == ld.LD_EINVAL
+    unstable = ld.make_query(W.single_large("SE"), 1e-2)
+    arr = (ld.Query * 1)(unstable)
+    assert lib.mlmc_estimate_batch(arr, 1, None, res) == ld.LD_EUNSTABLE
+    assert lib.mlmc_estimate_batch(arr, 0, None, res) == ld.LD_EINVAL
