@@ -4,8 +4,12 @@ One step = one full adaptive MLMC estimate (all levels, the driver's iterations,
 level kernels and the FP64 planning) of the large single-estimate workload: neutral
 boundary layer, BAOAB, release at 500 m with Gaussian w0, T = 1000 s, dt_0 = T/8,
 levels 0..12, relative eps 1e-4, E[Z(T)], FP32 paths with FP64 compensated sums.
+The line also carries a short serving run (Poisson arrivals, continuous batching,
+p50/p99 latency, FP32 against plain one-at-a-time FP64).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32|fp64]
+    python bench.py --workload batched      # 64 estimators in one engine
+    python bench.py --workload serving --rate 100 --duration 60
 
 Prints one JSON line. The CPU baseline times the oracle on a bounded sample of the
 same workload on this host's cores.
@@ -82,8 +86,156 @@ def cpu_baseline(cfg, N_levels, target_steps=2.5e8):
                       f"{f:.3g} (N_l = {counts}), {steps:.3g} coupled fine steps, FP64, {dt:.1f} s"}
 
 
+def _pct(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs), q)) if xs else None
+
+
+# Per-query cost budget of the serving runs (coupled fine steps): about 25 ms of the
+# FP32 path at full device rate and 10x the costliest well-posed query of the mix.
+SERVE_MAX_FINE_STEPS = 1e10
+
+
+def serve_trace(ld, arrivals, policy, precision, n_init, max_seconds=None, drain_seconds=120.0,
+                **engine_kw):
+    """Replays an arrival trace against a server in real time: each query is submitted
+    at its arrival time, latency = completion - scheduled arrival. With max_seconds,
+    submission stops at that time of the trace. Queries not done drain_seconds after
+    the last submission are reported as unfinished (an overloaded server is not waited
+    on for ever); their latency counts as the time they had waited by then."""
+    queries = [ld.make_query(a["problem"], a["eps"], eps_is_relative=a["eps_is_relative"],
+                             N_init=n_init, max_fine_steps=SERVE_MAX_FINE_STEPS) for a in arrivals]
+    with ld.Server(policy=policy, precision=precision, **engine_kw) as srv:
+        t0 = ld.clock() + 0.05
+        sent = []
+        next_note = t0 + 10.0
+        for a, q in zip(arrivals, queries):
+            if max_seconds is not None and a["arrival"] > max_seconds:
+                break
+            target = t0 + a["arrival"]
+            while True:
+                now = ld.clock()
+                dt = target - now
+                if dt <= 0:
+                    break
+                time.sleep(min(dt, 0.002) if dt > 0.0005 else 0)
+            sent.append((srv.submit(q), target))
+            if ld.clock() > next_note:
+                st = srv.stats()
+                print(json.dumps({"progress": f"{policy}/{precision} submitting",
+                                  "submitted": st["submitted"], "completed": st["completed"],
+                                  "running": st["running"], "queued": st["queued"]}),
+                      file=sys.stderr, flush=True)
+                next_note += 10.0
+        deadline = ld.clock() + drain_seconds
+        lat, queue_wait, steps, statuses = [], [], 0.0, {}
+        unfinished = 0
+        t_last = t0
+        for ticket, target in sent:
+            got = None
+            while got is None:
+                left = deadline - ld.clock()
+                if left <= 0:
+                    break
+                got = srv.wait(ticket, timeout=min(left, 10.0))
+                if got is None:
+                    st = srv.stats()
+                    print(json.dumps({"progress": f"{policy}/{precision} draining",
+                                      "completed": st["completed"], "of": len(sent),
+                                      "running": st["running"], "queued": st["queued"]}),
+                          file=sys.stderr, flush=True)
+            if got is None:
+                unfinished += 1
+                lat.append(ld.clock() - target)
+                continue
+            r, tm = got
+            lat.append(tm["t_done"] - target)
+            queue_wait.append(tm["t_admit"] - tm["t_submit"])
+            steps += r["fine_steps"]
+            statuses[r["status"]] = statuses.get(r["status"], 0) + 1
+            t_last = max(t_last, tm["t_done"])
+        st = srv.stats()
+    span = (ld.clock() if unfinished else t_last) - t0
+    return {"policy": policy, "precision": precision, "queries": len(sent),
+            "unfinished": unfinished,
+            "p50_ms": 1e3 * _pct(lat, 50), "p99_ms": 1e3 * _pct(lat, 99),
+            "mean_ms": 1e3 * sum(lat) / len(lat), "max_ms": 1e3 * max(lat),
+            "admission_wait_p99_ms": 1e3 * _pct(queue_wait, 99) if queue_wait else None,
+            "queries_per_s": (len(sent) - unfinished) / span, "span_s": span,
+            "coupled_steps_per_s": steps / span, "iterations": st["iterations"],
+            "max_running": st["max_running"], "max_queued": st["max_queued"],
+            "device_busy_frac": st["device_seconds"] / span,
+            "status_counts": {str(k): v for k, v in sorted(statuses.items())}}
+
+
+def serving_report(ld, rate, duration, seed, n_init, fifo_seconds=None, precisions=("fp32", "fp64")):
+    arrivals = W.poisson_arrivals(rate, duration, seed=seed)
+    out = {"rate_qps": rate, "duration_s": duration, "arrivals": len(arrivals),
+           "eps_range": [3e-4, 1e-2], "N_init": n_init, "max_fine_steps": SERVE_MAX_FINE_STEPS,
+           "runs": []}
+    for prec in precisions:
+        out["runs"].append(serve_trace(ld, arrivals, "batch", prec, n_init))
+        print(json.dumps({"progress": "serving", **out["runs"][-1]}), file=sys.stderr, flush=True)
+    out["runs"].append(serve_trace(ld, arrivals, "fifo", "fp64", n_init, max_seconds=fifo_seconds))
+    print(json.dumps({"progress": "serving", **out["runs"][-1]}), file=sys.stderr, flush=True)
+    return out
+
+
+BATCHED_N_INIT = 1000
+
+
+def batched_report(ld, steps, warmup):
+    """64 independent estimators (mixed release height, tolerance, integrator and QoI)
+    in one engine: autotuned FP32, the same options in FP64, and the same queries one
+    at a time through mlmc_estimate in FP64."""
+    import torch
+    spec = W.batched_estimators(64)
+    queries = [ld.make_query(q["problem"], q["eps"], eps_is_relative=q["eps_is_relative"],
+                             N_init=BATCHED_N_INIT) for q in spec]
+    best, t_tune = ld.autotune(queries, reps=1, precision="fp32")
+    res = {}
+    for prec in ("fp32", "fp64"):
+        o = ld.engine_opts(**dict(ld.opts_dict(best), precision=prec))
+        for _ in range(warmup):
+            ld.estimate_batch(queries, opts=o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            out = ld.estimate_batch(queries, opts=o)
+        dt = (time.perf_counter() - t0) / steps
+        fs = sum(r["fine_steps"] for r in out)
+        res[prec] = {"seconds": dt, "coupled_steps_per_s": fs / dt, "fine_steps": fs,
+                     "max_N_l": max(max(r["N"]) for r in out),
+                     "min_N_l": min(min(r["N"]) for r in out)}
+        if prec == "fp32":
+            est32 = [r["estimate"] for r in out]
+        else:
+            est64 = [r["estimate"] for r in out]
+    t0 = time.perf_counter()
+    seq = [ld.estimate(q["eps"], q["problem"], precision="fp64", eps_is_relative=q["eps_is_relative"],
+                       N_init=BATCHED_N_INIT) for q in spec]
+    t_seq = time.perf_counter() - t0
+    res["fp64_one_at_a_time"] = {"seconds": t_seq,
+                                 "coupled_steps_per_s": sum(r["fine_steps"] for r in seq) / t_seq}
+    # |FP32 - FP64| in units of each query's absolute tolerance
+    rel = [abs(a - b) / (q["eps"] * (abs(b) if q["eps_is_relative"] else 1.0))
+           for a, b, q in zip(est32, est64, spec)]
+    res["fp32_vs_fp64_over_eps_max"] = max(rel)
+    res["autotuned"] = {k: v for k, v in ld.opts_dict(best).items() if k != "precision"}
+    res["autotune_s"] = t_tune
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="single_large", choices=["single_large", "batched", "serving"])
+    ap.add_argument("--rate", type=float, default=100.0, help="serving: arrivals per second")
+    ap.add_argument("--duration", type=float, default=60.0, help="serving: seconds of arrivals")
+    ap.add_argument("--fifo-seconds", type=float, default=None,
+                    help="serving: stop feeding the FIFO baseline after this many seconds")
+    ap.add_argument("--n-init", type=int, default=1000, help="serving: first batch per level")
+    ap.add_argument("--serve-seconds", type=float, default=5.0,
+                    help="single_large: seconds of the short serving run (0 = none)")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
@@ -112,6 +264,30 @@ def main():
     import paper_1612_07717_amd as ld
 
     torch.cuda.set_device(0)
+    if args.workload == "serving":
+        rep = serving_report(ld, args.rate, args.duration, seed=11, n_init=args.n_init,
+                             fifo_seconds=args.fifo_seconds)
+        batch32 = rep["runs"][0]
+        print(json.dumps({"metric": "query p50/p99 latency", "value": batch32["p99_ms"],
+                          "unit": "ms (p99, FP32 continuous batching)", "n_gpus": 1,
+                          "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+                          "config": {"workload": f"serving: Poisson arrivals at {args.rate:g} "
+                                                 f"queries/s for {args.duration:g} s, release "
+                                                 "U[50,950] m, relative eps log-uniform "
+                                                 "[3e-4,1e-2], integrator and QoI mixed"},
+                          "serving": rep}), flush=True)
+        return
+    if args.workload == "batched":
+        rep = batched_report(ld, args.steps, args.warmup)
+        print(json.dumps({"metric": "coupled particle-steps/s", "value": rep["fp32"]["coupled_steps_per_s"],
+                          "unit": "coupled particle-steps/s", "n_gpus": 1, "steps": args.steps,
+                          "warmup": args.warmup, "ms_per_step": 1e3 * rep["fp32"]["seconds"],
+                          "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+                          "config": {"workload": "64 estimators: release U[50,950] m, relative eps "
+                                                 "log-uniform [1e-3,1e-2], integrator and QoI mixed, "
+                                                 "one engine, tiles autotuned"},
+                          "batched": rep}), flush=True)
+        return
     cfg = W.single_large(args.integrator)
     L = W.SINGLE_LARGE_LEVELS
     eps = W.SINGLE_LARGE_EPS_REL
@@ -179,6 +355,13 @@ def main():
                      "ops_per_coupled_step": ops,
                      "avg_launch_ms": 1e3 * dev_s / launches},
     }
+    if args.serve_seconds > 0:
+        rep = serving_report(ld, 100.0, args.serve_seconds, seed=11, n_init=args.n_init)
+        line["serving"] = {k: rep[k] for k in ("rate_qps", "duration_s", "arrivals", "N_init")}
+        for r in rep["runs"]:
+            key = f"{r['policy']}_{r['precision']}"
+            line["serving"][key] = {k: r[k] for k in ("p50_ms", "p99_ms", "queries_per_s",
+                                                      "coupled_steps_per_s", "max_running")}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(dict(cfg), last["N"])
     print(json.dumps(line), flush=True)

@@ -210,6 +210,9 @@ typedef struct {
     uint64_t seed;
     int32_t max_iter;        /* default 100 */
     int32_t reserved;
+    double max_fine_steps;   /* cost budget: stop (LD_WARN_NOT_CONVERGED) rather than draw
+                                a batch that would take sum_l N_l M_l above this; the
+                                first batch always runs. 0 = no budget (default) */
     void* d_workspace;       /* NULL: allocated and freed inside the call */
     size_t workspace_bytes;
     void* hip_stream;
@@ -287,6 +290,7 @@ typedef struct {
     int32_t L_min, L_max, fixed_L, max_iter;
     uint64_t N_init;
     double alpha;
+    double max_fine_steps;        /* cost budget as in ld_estimate_opts (0 = none) */
 } ld_query;
 
 void ld_engine_default_opts(ld_engine_opts* opts);
@@ -321,6 +325,72 @@ int mlmc_estimate_batch(const ld_query* queries, int32_t n, const ld_engine_opts
    candidate, the median counts. */
 int ld_engine_autotune(const ld_query* queries, int32_t n, const ld_engine_opts* base,
                        int32_t reps, ld_engine_opts* best, double* best_seconds);
+
+/* ---- serving: a request loop over the engine -------------------------------------- */
+
+/* A server owns one engine and a worker thread. Clients submit queries from any
+   thread; submission only validates and enqueues (it never waits for the device).
+   The worker admits queued queries in arrival order whenever the engine has a free
+   slot within its HBM budget, runs one engine iteration over all admitted queries,
+   hands finished results to their tickets and frees their slots; queries that arrive
+   while an iteration runs join at the next one (continuous batching). Each query's
+   per-level running sums, and with them its next Philox sample index per level
+   (n + n_nonfinite), stay in device memory until it finishes. Because a query's
+   tiles and merges depend on the query alone, its result does not depend on the
+   traffic it shared the device with.
+
+   Policy LD_SERVE_FIFO is the plain comparison point: the worker takes one query at a
+   time, in arrival order, through mlmc_estimate (no batching). */
+
+enum { LD_SERVE_BATCH = 0, LD_SERVE_FIFO = 1 };
+
+typedef struct ld_server ld_server;   /* opaque */
+
+typedef struct {
+    ld_engine_opts engine;        /* engine of LD_SERVE_BATCH; for LD_SERVE_FIFO only
+                                     engine.precision is used */
+    int32_t policy;               /* LD_SERVE_BATCH (default) or LD_SERVE_FIFO */
+    int32_t max_queued;           /* submissions beyond this many waiting queries get
+                                     LD_EBUSY (0 = no limit) */
+} ld_server_opts;
+
+/* Clock of the request times: seconds on a monotonic clock (steady, any origin). */
+typedef struct {
+    double t_submit;              /* ld_server_submit accepted the query */
+    double t_admit;               /* the query got a slot (FIFO: its estimate started) */
+    double t_done;                /* its result was ready */
+} ld_request_times;
+
+typedef struct {
+    int64_t submitted, completed, queued, running;
+    int64_t iterations;           /* engine iterations (FIFO: estimates) */
+    int32_t max_running, max_queued;
+    double busy_seconds;          /* worker wall time inside iterations / estimates */
+    double device_seconds;        /* time inside the path kernels (HIP events) */
+    double fine_steps;            /* coupled particle-steps of all finished work */
+} ld_server_stats;
+
+void ld_server_default_opts(ld_server_opts* opts);
+/* Creates the engine (LD_SERVE_BATCH) or a workspace and stream (LD_SERVE_FIFO) on the
+   current device and starts the worker thread. */
+int ld_server_create(const ld_server_opts* opts, ld_server** out);
+/* Stops the worker after its current iteration and frees everything; queries not yet
+   collected are dropped. No other call on this server may run concurrently. */
+void ld_server_destroy(ld_server* server);
+/* Thread-safe. Validates the query (LD_EINVAL / LD_EUNSTABLE as mlmc_estimate) and
+   enqueues it; *ticket identifies it for ld_server_wait. LD_EBUSY if max_queued
+   queries are waiting; a stored error status if the worker has failed. */
+int ld_server_submit(ld_server* server, const ld_query* query, int64_t* ticket);
+/* Thread-safe. Waits up to timeout_s seconds (< 0: no limit, 0: poll) for the ticket's
+   result. Returns LD_PENDING on timeout; otherwise the query's final status (as
+   mlmc_estimate) with out (and times, if not NULL) filled, after which the ticket is
+   gone. LD_EINVAL for an unknown ticket. */
+int ld_server_wait(ld_server* server, int64_t ticket, double timeout_s, ld_estimate_result* out,
+                   ld_request_times* times);
+/* Thread-safe snapshot of the counters. */
+int ld_server_stats_get(ld_server* server, ld_server_stats* out);
+/* The clock of ld_request_times, for clients that time arrivals. */
+double ld_server_clock(void);
 
 /* ---- errors --------------------------------------------------------------------- */
 const char* ld_strerror(int status);

@@ -31,7 +31,10 @@ EXPORTED = ["mlmc_level_sums_workspace", "mlmc_level_sums", "mlmc_level_sums_bat
             "ld_engine_default_opts", "ld_engine_create", "ld_engine_destroy", "ld_engine_submit",
             "ld_engine_step", "ld_engine_result", "ld_engine_release", "ld_engine_stats",
             "mlmc_estimate_batch", "ld_engine_autotune",
+            "ld_server_default_opts", "ld_server_create", "ld_server_destroy", "ld_server_submit",
+            "ld_server_wait", "ld_server_stats_get", "ld_server_clock",
             "ld_strerror", "ld_last_error"]
+SERVE_POLICIES = {"batch": 0, "fifo": 1}
 LD_PENDING, LD_EBUSY = 2, -7
 
 
@@ -93,6 +96,7 @@ class EstimateOpts(C.Structure):
                 ("fixed_N", C.c_int32), ("eps_is_relative", C.c_int32), ("N_init", C.c_uint64),
                 ("alpha", C.c_double), ("precision", C.c_int32), ("stream_id", C.c_uint32),
                 ("seed", C.c_uint64), ("max_iter", C.c_int32), ("reserved", C.c_int32),
+                ("max_fine_steps", C.c_double),
                 ("d_workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
                 ("hip_stream", C.c_void_p)]
 
@@ -121,7 +125,22 @@ class Query(C.Structure):
     _fields_ = [("problem", Problem), ("integrator", C.c_int32), ("eps_is_relative", C.c_int32),
                 ("eps", C.c_double), ("L_min", C.c_int32), ("L_max", C.c_int32),
                 ("fixed_L", C.c_int32), ("max_iter", C.c_int32), ("N_init", C.c_uint64),
-                ("alpha", C.c_double)]
+                ("alpha", C.c_double), ("max_fine_steps", C.c_double)]
+
+
+class ServerOpts(C.Structure):
+    _fields_ = [("engine", EngineOpts), ("policy", C.c_int32), ("max_queued", C.c_int32)]
+
+
+class RequestTimes(C.Structure):
+    _fields_ = [("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("queued", C.c_int64),
+                ("running", C.c_int64), ("iterations", C.c_int64), ("max_running", C.c_int32),
+                ("max_queued", C.c_int32), ("busy_seconds", C.c_double),
+                ("device_seconds", C.c_double), ("fine_steps", C.c_double)]
 
 
 _lib = None
@@ -169,6 +188,16 @@ def load():
     lib.mlmc_estimate_batch.argtypes = [P(Query), C.c_int32, P(EngineOpts), P(EstimateResult)]
     lib.ld_engine_autotune.argtypes = [P(Query), C.c_int32, P(EngineOpts), C.c_int32,
                                        P(EngineOpts), P(C.c_double)]
+    lib.ld_server_default_opts.argtypes = [P(ServerOpts)]
+    lib.ld_server_default_opts.restype = None
+    lib.ld_server_create.argtypes = [P(ServerOpts), P(C.c_void_p)]
+    lib.ld_server_destroy.argtypes = [C.c_void_p]
+    lib.ld_server_destroy.restype = None
+    lib.ld_server_submit.argtypes = [C.c_void_p, P(Query), P(C.c_int64)]
+    lib.ld_server_wait.argtypes = [C.c_void_p, C.c_int64, C.c_double, P(EstimateResult),
+                                   P(RequestTimes)]
+    lib.ld_server_stats_get.argtypes = [C.c_void_p, P(ServerStats)]
+    lib.ld_server_clock.restype = C.c_double
     _lib = lib
     return lib
 
@@ -291,7 +320,7 @@ def level_samples(cfg, level, begin, n, precision="fp64", stream=None) -> np.nda
 
 def estimate_opts(cfg, *, precision="fp64", L_min=2, L_max=20, fixed_L=-1, fixed_N=False,
                   N_init=10000, eps_is_relative=False, alpha=1.0, max_iter=100,
-                  workspace=None, stream=None) -> EstimateOpts:
+                  max_fine_steps=0.0, workspace=None, stream=None) -> EstimateOpts:
     o = EstimateOpts()
     load().mlmc_estimate_default_opts(C.byref(o))
     o.release = make_release(cfg)
@@ -305,6 +334,7 @@ def estimate_opts(cfg, *, precision="fp64", L_min=2, L_max=20, fixed_L=-1, fixed
     o.stream_id = int(cfg["stream_id"])
     o.seed = int(cfg["seed"])
     o.max_iter = int(max_iter)
+    o.max_fine_steps = float(max_fine_steps)
     if workspace is not None:
         o.d_workspace = workspace.data_ptr()
         o.workspace_bytes = workspace.numel() * workspace.element_size()
@@ -379,11 +409,11 @@ def _result_dict(r: EstimateResult, rc: int) -> dict:
 
 
 def make_query(cfg: dict, eps: float, *, eps_is_relative=True, L_min=2, L_max=20, fixed_L=-1,
-               N_init=10000, alpha=1.0, max_iter=100) -> Query:
+               N_init=10000, alpha=1.0, max_iter=100, max_fine_steps=0.0) -> Query:
     return Query(problem=make_problem(cfg), integrator=INTEGRATORS[cfg["integrator"]],
                  eps_is_relative=int(bool(eps_is_relative)), eps=float(eps), L_min=L_min,
                  L_max=L_max, fixed_L=fixed_L, max_iter=max_iter, N_init=int(N_init),
-                 alpha=float(alpha))
+                 alpha=float(alpha), max_fine_steps=float(max_fine_steps))
 
 
 def engine_opts(*, precision="fp32", max_queries=256, hbm_budget_bytes=1 << 30, blocks_per_cu=8,
@@ -493,3 +523,68 @@ def opts_dict(o: EngineOpts) -> dict:
             "hbm_budget_bytes": o.hbm_budget_bytes, "blocks_per_cu": o.blocks_per_cu,
             "target_tiles": o.target_tiles, "pipe_max_samples": o.pipe_max_samples,
             "pipe_min_steps": o.pipe_min_steps, "use_graph": bool(o.use_graph)}
+
+
+class Server:
+    """ld_server: a worker thread that serves queries with continuous batching
+    (policy "batch") or one at a time through mlmc_estimate (policy "fifo").
+    submit() only enqueues; wait() blocks until a query's result is ready."""
+
+    def __init__(self, policy="batch", max_queued=0, opts: EngineOpts | None = None, **kw):
+        _torch()
+        self._lib = load()
+        so = ServerOpts()
+        self._lib.ld_server_default_opts(C.byref(so))
+        so.engine = opts if opts is not None else engine_opts(**kw)
+        so.policy = SERVE_POLICIES[policy]
+        so.max_queued = int(max_queued)
+        h = C.c_void_p()
+        _check(self._lib.ld_server_create(C.byref(so), C.byref(h)))
+        self._h = h
+
+    def close(self):
+        if self._h:
+            self._lib.ld_server_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, query: Query):
+        """Ticket of the enqueued query, or None if the admission queue is full."""
+        t = C.c_int64()
+        rc = self._lib.ld_server_submit(self._h, C.byref(query), C.byref(t))
+        if rc == LD_EBUSY:
+            return None
+        _check(rc)
+        return int(t.value)
+
+    def wait(self, ticket: int, timeout: float | None = None):
+        """(result dict, times dict) once finished; None if timeout (seconds) passed."""
+        r, tm = EstimateResult(), RequestTimes()
+        rc = self._lib.ld_server_wait(self._h, int(ticket), -1.0 if timeout is None else float(timeout),
+                                      C.byref(r), C.byref(tm))
+        if rc == LD_PENDING:
+            return None
+        _check(rc, ok=(LD_OK, LD_WARN_NOT_CONVERGED, LD_ENONFINITE))
+        return _result_dict(r, rc), {"t_submit": tm.t_submit, "t_admit": tm.t_admit,
+                                     "t_done": tm.t_done}
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(self._lib.ld_server_stats_get(self._h, C.byref(st)))
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_}
+
+
+def clock() -> float:
+    """ld_server_clock: the monotonic clock of the request times."""
+    return float(load().ld_server_clock())

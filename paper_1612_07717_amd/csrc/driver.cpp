@@ -20,6 +20,15 @@
 
 using namespace ldm;
 
+bool ldm::exceeds_budget(double max_fine_steps, int32_t M0, const uint64_t* drawn, const uint64_t* dn,
+                         int32_t L) {
+    if (!(max_fine_steps > 0.0)) return false;
+    double cost = 0.0;
+    for (int32_t l = 0; l <= L && l < LD_MAX_LEVELS; ++l)
+        cost += ((double)drawn[l] + (double)dn[l]) * std::ldexp((double)M0, l);
+    return cost > max_fine_steps;
+}
+
 namespace {
 
 double cost_of_level(int32_t M0, int32_t l) { return std::ldexp((double)M0, l); }
@@ -199,6 +208,7 @@ int mlmc_estimate(double eps, const ld_qoi* qoi, ld_integrator integrator, const
     if (L0 < 0 || L0 >= LD_MAX_LEVELS || opts.L_max < L0 || opts.L_max >= LD_MAX_LEVELS)
         return fail(LD_EINVAL, "need 0 <= L_min <= L_max < LD_MAX_LEVELS");
     if (opts.N_init < 2) return fail(LD_EINVAL, "N_init must be >= 2");
+    if (!(opts.max_fine_steps >= 0.0)) return fail(LD_EINVAL, "max_fine_steps must be >= 0");
     rc = check_stability(&prob, integrator, 0);
     if (rc != LD_OK) return rc;
 
@@ -282,6 +292,7 @@ int mlmc_estimate(double eps, const ld_qoi* qoi, ld_integrator integrator, const
         mlmc_plan(&pin, &plan);
         ++iter;
         if (plan.status != 0 || iter >= max_iter) break;
+        if (exceeds_budget(opts.max_fine_steps, opts.M0, drawn, plan.dn, plan.L)) break;
         pin.L = plan.L;
         std::memcpy(dn, plan.dn, sizeof dn);
     }

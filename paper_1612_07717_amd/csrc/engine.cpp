@@ -81,19 +81,7 @@ struct ld_engine {
     double fine_steps = 0.0;
 };
 
-namespace {
-
-void release_resources(ld_engine* e) {
-    if (e->graph) (void)hipGraphExecDestroy(e->graph);
-    if (e->ev0) (void)hipEventDestroy(e->ev0);
-    if (e->ev1) (void)hipEventDestroy(e->ev1);
-    if (e->d_base) (void)hipFree(e->d_base);
-    if (e->h_hdr) (void)hipHostFree(e->h_hdr);
-    if (e->h_ranges) (void)hipHostFree(e->h_ranges);
-    if (e->h_tiles) (void)hipHostFree(e->h_tiles);
-    if (e->h_running) (void)hipHostFree(e->h_running);
-    if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
-}
+namespace ldm {
 
 int validate_query(const ld_query* qq) {
     if (qq == nullptr) return fail(LD_EINVAL, "query is NULL");
@@ -106,9 +94,26 @@ int validate_query(const ld_query* qq) {
     if (L0 < 0 || L0 >= LD_MAX_LEVELS || qq->L_max < L0 || qq->L_max >= LD_MAX_LEVELS)
         return fail(LD_EINVAL, "need 0 <= L_min <= L_max < LD_MAX_LEVELS");
     if (qq->N_init < 2) return fail(LD_EINVAL, "N_init must be >= 2");
+    if (!(qq->max_fine_steps >= 0.0)) return fail(LD_EINVAL, "max_fine_steps must be >= 0");
     if (std::ldexp((double)qq->problem.M0, qq->L_max) > 2147483648.0)
         return fail(LD_EINVAL, "M0 * 2^L_max must not exceed 2^31");
     return check_stability(&qq->problem, qq->integrator, 0);
+}
+
+}  // namespace ldm
+
+namespace {
+
+void release_resources(ld_engine* e) {
+    if (e->graph) (void)hipGraphExecDestroy(e->graph);
+    if (e->ev0) (void)hipEventDestroy(e->ev0);
+    if (e->ev1) (void)hipEventDestroy(e->ev1);
+    if (e->d_base) (void)hipFree(e->d_base);
+    if (e->h_hdr) (void)hipHostFree(e->h_hdr);
+    if (e->h_ranges) (void)hipHostFree(e->h_ranges);
+    if (e->h_tiles) (void)hipHostFree(e->h_tiles);
+    if (e->h_running) (void)hipHostFree(e->h_running);
+    if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
 }
 
 // Tiles of one range; the rule depends on the range alone.
@@ -474,7 +479,8 @@ int ld_engine_step(ld_engine* e, int32_t* n_active) {
         mlmc_plan(&pin, &qu.plan);
         qu.iterations += 1;
         const int max_iter = qu.q.max_iter > 0 ? qu.q.max_iter : 100;
-        if (qu.plan.status != 0 || qu.iterations >= max_iter) {
+        if (qu.plan.status != 0 || qu.iterations >= max_iter ||
+            exceeds_budget(qu.q.max_fine_steps, qu.prob.M0, qu.drawn, qu.plan.dn, qu.plan.L)) {
             finish_query(qu, qu.plan.status);
         } else {
             qu.L = qu.plan.L;

@@ -12,6 +12,12 @@ int fail(int status, const std::string& msg);
 
 // Validates a problem; returns LD_OK or LD_EINVAL (message set).
 int validate_problem(const ld_problem* p);
+// True if drawing dn more samples (levels 0..L) on top of `drawn` would take the
+// coupled fine steps sum_l N_l M0 2^l above max_fine_steps (> 0); false without a budget.
+bool exceeds_budget(double max_fine_steps, int32_t M0, const uint64_t* drawn, const uint64_t* dn,
+                    int32_t L);
+// Validates an engine query as mlmc_estimate validates its arguments (engine.cpp).
+int validate_query(const ld_query* q);
 // Symplectic Euler is stable only for lambda h < 2 (Sec. 3.1); returns LD_EUNSTABLE if
 // a step of `level` violates it, else LD_OK.
 int check_stability(const ld_problem* p, ld_integrator integ, int32_t level);

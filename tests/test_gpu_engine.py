@@ -29,26 +29,31 @@ def _mixed_configs(n, seed=3):
     """Neutral-layer queries of the batched workload, with tolerances loose enough for
     a quick test."""
     qs = W.batched_estimators(n, seed=seed, eps_range=(5e-3, 2e-2))
-    return [(q["problem"], q["eps"]) for q in qs]
+    return [(q["problem"], q["eps"], q["eps_is_relative"]) for q in qs]
+
+
+def _query(c, e, rel, **kw):
+    return ld.make_query(c, e, eps_is_relative=rel, **kw)
 
 
 def test_batch_equals_single_estimates():
     cfgs = _mixed_configs(6)
-    qs = [ld.make_query(c, e, N_init=2000, L_max=10) for c, e in cfgs]
+    qs = [_query(c, e, rel, N_init=2000, L_max=10) for c, e, rel in cfgs]
     batch = ld.estimate_batch(qs, precision="fp32")
-    for (c, e), b in zip(cfgs, batch):
-        s = ld.estimate(e, c, precision="fp32", eps_is_relative=True, N_init=2000, L_max=10)
+    for (c, e, rel), b in zip(cfgs, batch):
+        s = ld.estimate(e, c, precision="fp32", eps_is_relative=rel, N_init=2000, L_max=10)
         say(f"batch {c['integrator']} z0={c['z0']:.0f} {c['qoi']}: {b['estimate']:.6f} N={b['N']}")
         assert b["N"] == s["N"] and b["L"] == s["L"]
         assert b["estimate"] == s["estimate"]
         assert b["status"] == s["status"] == 1
+    assert not all(rel for _, _, rel in cfgs) and any(rel for _, _, rel in cfgs)
 
 
 def test_alone_equals_mixed_bitwise():
     cfgs = _mixed_configs(12, seed=5)
-    q0 = ld.make_query(*cfgs[0], N_init=2000, L_max=10)
+    q0 = _query(*cfgs[0], N_init=2000, L_max=10)
     alone = ld.estimate_batch([q0], precision="fp32")[0]
-    mixed = ld.estimate_batch([ld.make_query(c, e, N_init=2000, L_max=10) for c, e in cfgs],
+    mixed = ld.estimate_batch([_query(c, e, rel, N_init=2000, L_max=10) for c, e, rel in cfgs],
                               precision="fp32")[0]
     assert alone["N"] == mixed["N"]
     assert alone["estimate"] == mixed["estimate"]
@@ -70,7 +75,7 @@ def test_fp64_engine_matches_oracle_driver():
 
 def test_admission_release_and_graph_equivalence():
     cfgs = _mixed_configs(7, seed=9)
-    qs = [ld.make_query(c, e, N_init=2000, L_max=10) for c, e in cfgs]
+    qs = [_query(c, e, rel, N_init=2000, L_max=10) for c, e, rel in cfgs]
     ref = ld.estimate_batch(qs, precision="fp32", use_graph=False)
     with ld.Engine(precision="fp32", max_queries=3) as eng:
         handles = [eng.submit(q) for q in qs[:3]]
@@ -103,7 +108,7 @@ def test_admission_release_and_graph_equivalence():
 
 def test_autotuner_returns_a_valid_configuration():
     cfgs = _mixed_configs(4, seed=13)
-    qs = [ld.make_query(c, e, N_init=1000, L_max=8) for c, e in cfgs]
+    qs = [_query(c, e, rel, N_init=1000, L_max=8) for c, e, rel in cfgs]
     best, t = ld.autotune(qs, reps=1, precision="fp32")
     d = ld.opts_dict(best)
     say(f"autotune best {d} in {t * 1e3:.2f} ms")

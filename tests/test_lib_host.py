@@ -55,7 +55,8 @@ def test_struct_layouts_match_header(tmp_path):
                "ld_level_range": ld.LevelRange, "ld_plan_in": ld.PlanIn,
                "ld_plan_out": ld.PlanOut, "ld_estimate_opts": ld.EstimateOpts,
                "ld_estimate_result": ld.EstimateResult, "ld_engine_opts": ld.EngineOpts,
-               "ld_query": ld.Query}
+               "ld_query": ld.Query, "ld_server_opts": ld.ServerOpts,
+               "ld_request_times": ld.RequestTimes, "ld_server_stats": ld.ServerStats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ldmlmc.h"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -157,7 +158,7 @@ def test_estimate_argument_errors(lib):
 
 
 def test_strerror_covers_all_codes(lib):
-    for code in (0, 1, -1, -2, -3, -4, -5, -6):
+    for code in (0, 1, 2, -1, -2, -3, -4, -5, -6, -7):
         assert lib.ld_strerror(code).decode() != "unknown status"
     assert lib.ld_strerror(-99).decode() == "unknown status"
 
@@ -172,3 +173,32 @@ def test_batch_validates_queries_before_device_use(lib):
     arr = (ld.Query * 1)(unstable)
     assert lib.mlmc_estimate_batch(arr, 1, None, res) == ld.LD_EUNSTABLE
     assert lib.mlmc_estimate_batch(arr, 0, None, res) == ld.LD_EINVAL
+
+
+def test_server_rejects_bad_arguments_without_device(lib):
+    """Server entry points check their arguments before any device use; creating a
+    server with no GPU present fails with a status, not a crash."""
+    h = C.c_void_p()
+    bad = ld.ServerOpts()
+    lib.ld_server_default_opts(C.byref(bad))
+    bad.policy = 7
+    assert lib.ld_server_create(C.byref(bad), C.byref(h)) == ld.LD_EINVAL
+    bad.policy = 0
+    bad.max_queued = -1
+    assert lib.ld_server_create(C.byref(bad), C.byref(h)) == ld.LD_EINVAL
+    t = C.c_int64()
+    q = ld.make_query(W.neutral(300.0, "GL"), 1e-2)
+    assert lib.ld_server_submit(None, C.byref(q), C.byref(t)) == ld.LD_EINVAL
+    r = ld.EstimateResult()
+    assert lib.ld_server_wait(None, 0, 0.0, C.byref(r), None) == ld.LD_EINVAL
+    a, b = lib.ld_server_clock(), lib.ld_server_clock()
+    assert b >= a
+
+
+def test_negative_cost_budget_is_rejected(lib):
+    q = ld.make_query(W.neutral(300.0, "GL"), 1e-2, max_fine_steps=-1.0)
+    res = (ld.EstimateResult * 1)()
+    assert lib.mlmc_estimate_batch((ld.Query * 1)(q), 1, None, res) == ld.LD_EINVAL
+    with pytest.raises(ld.LdError) as e:
+        ld.estimate(1e-2, W.neutral(300.0, "GL"), max_fine_steps=-1.0)
+    assert e.value.status == ld.LD_EINVAL
