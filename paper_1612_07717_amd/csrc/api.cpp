@@ -110,6 +110,7 @@ int make_kproblem(const ld_problem* p, ld_integrator integ, KProblem* kp) {
     kp->z0 = p->release.z0;
     kp->w0 = p->release.w0;
     kp->su_z0 = sigma_u_at(f, p->release.z0);
+    kp->lam_max = lambda_max(f);
     kp->release = p->release.kind;
     kp->qoi_kind = p->qoi.kind;
     kp->r = p->qoi.r;

@@ -60,6 +60,7 @@ struct Math<float> {
     static __device__ __forceinline__ bool outside(float x, float H) {
         return __float_as_uint(x) > __float_as_uint(H);
     }
+
     // expm1 by argument reduction x = k ln2 + r, |r| <= ln2/2 (Cody & Waite's two-part
     // ln2), the Taylor series of expm1(r) to degree 7 (truncation < 2e-8 relative), and
     // expm1(x) = 2^k expm1(r) + (2^k - 1), which has no cancellation for k != 0.
@@ -79,6 +80,17 @@ struct Math<float> {
         const float two_k = __builtin_amdgcn_ldexpf(1.0f, ki);
         return __builtin_fmaf(two_k, p, two_k - 1.0f);
     }
+    // expm1(z) for |z| <= kSmallZ: the Taylor series to degree 5 (truncation below
+    // 1.5e-9 relative), evaluated in Estrin form so that only three dependent
+    // operations follow z: z + z^2 (1/2 + z/6) + z^4 (1/24 + z/120).
+    static constexpr float kSmallZ = 0.0625f;
+    static __device__ __forceinline__ float expm1_small(float z) {
+        const float z2 = z * z;
+        const float a = __builtin_fmaf(z, 1.0f / 6.0f, 0.5f);
+        const float b = __builtin_fmaf(z, 1.0f / 120.0f, 1.0f / 24.0f);
+        const float z4 = z2 * z2;
+        return __builtin_fmaf(z4, b, __builtin_fmaf(z2, a, z));
+    }
 };
 
 template <>
@@ -90,6 +102,18 @@ struct Math<double> {
         return __hiloint2double(__double2hiint(v) ^ (int)mask, __double2loint(v));
     }
     static __device__ __forceinline__ double expm1_(double x) { return expm1(x); }
+    // expm1(z) for |z| <= kSmallZ: the Taylor series to degree 7 (truncation below
+    // 1e-17 relative) in Estrin form:
+    // z + z^2 (1/2 + z/6) + z^4 ((1/24 + z/120) + z^2 (1/720 + z/5040)).
+    static constexpr double kSmallZ = 0.015625;
+    static __device__ __forceinline__ double expm1_small(double z) {
+        const double z2 = z * z;
+        const double a = fma(z, 1.0 / 6.0, 0.5);
+        const double b = fma(z, 1.0 / 120.0, 1.0 / 24.0);
+        const double c = fma(z, 1.0 / 5040.0, 1.0 / 720.0);
+        const double z4 = z2 * z2;
+        return fma(z4, fma(z2, c, b), fma(z2, a, z));
+    }
     static __device__ __forceinline__ double clamp_(double x, double lo, double hi) {
         return fmin(fmax(x, lo), hi);
     }
@@ -98,6 +122,7 @@ struct Math<double> {
         inv = 1.0 / d;
     }
     static __device__ __forceinline__ bool outside(double x, double H) { return x < 0.0 || x > H; }
+
 };
 
 // Per-(problem, level) constants in the path precision.
@@ -188,7 +213,7 @@ struct Path {
     R x, u;
     uint32_t sgn;   // reflection sign S as a sign-bit mask (0: S = +1)
     R a, b;         // drift coefficients at x (BAOAB carries them to the next step)
-    bool bad;
+    bool bad;       // ran away (more than kFoldMax reflections): non-finite
 };
 
 // Fold into [0, H]; 0 and H are inside. More than kFoldMax reflections in one fold
@@ -212,10 +237,26 @@ __device__ __forceinline__ void fold(Path<R>& p, R H) {
     }
 }
 
+
+// expm1(-lambda h) of an O-step. SMALL: lambda_max h <= kSmallZ for this step size, so
+// the short series is exact to rounding for every X. The choice is made once per path
+// loop (it depends on the level and the step size only), never inside a step.
+template <typename R, bool SMALL>
+__device__ __forceinline__ R o_step_expm1(R z) {
+    if (SMALL) return Math<R>::expm1_small(z);
+    return Math<R>::expm1_(z);
+}
+
+// True if the O-steps of size h may use the short expm1 series.
+template <typename R>
+__device__ __forceinline__ bool small_steps(const KProblem& kp, double h) {
+    return kp.lam_max * h <= (double)Math<R>::kSmallZ;
+}
+
 // One step of size h. COARSE: xi is the combined extended noise and the physical noise
 // is S xi; otherwise xi is the physical noise and `tilde` receives S xi. `w` receives
-// e^{-lambda h} of the O-step (GL, BAOAB).
-template <typename R, int INTEG, int PROF, bool COARSE>
+// e^{-lambda h} of the O-step (GL, BAOAB). SMALL: see o_step_expm1.
+template <typename R, int INTEG, int PROF, bool COARSE, bool SMALL>
 __device__ __forceinline__ void step(const Consts<R>& c, Path<R>& p, R h, R hh, R xi,
                                      R& tilde, R& w) {
     if (INTEG == KINTEG_SE) {                                        // Eq. (8)
@@ -234,7 +275,7 @@ __device__ __forceinline__ void step(const Consts<R>& c, Path<R>& p, R h, R hh, 
         coeffs_at<R, PROF>(c, p.x, su, lam, a, b);
         const R noise = COARSE ? Math<R>::flip(xi, p.sgn) : xi;
         if (!COARSE) tilde = Math<R>::flip(xi, p.sgn);
-        const R e1 = Math<R>::expm1_(-lam * h);
+        const R e1 = o_step_expm1<R, SMALL>(-lam * h);
         w = (R)1 + e1;
         const R amp = su * Math<R>::sqrt_(-e1 * ((R)2 + e1));
         const R us = w * p.u + amp * noise;                          // O
@@ -249,7 +290,7 @@ __device__ __forceinline__ void step(const Consts<R>& c, Path<R>& p, R h, R hh, 
         profile_at<R, PROF>(c, p.x, su, lam);
         const R noise = COARSE ? Math<R>::flip(xi, p.sgn) : xi;
         if (!COARSE) tilde = Math<R>::flip(xi, p.sgn);
-        const R e1 = Math<R>::expm1_(-lam * h);
+        const R e1 = o_step_expm1<R, SMALL>(-lam * h);
         w = (R)1 + e1;
         const R amp = su * Math<R>::sqrt_(-e1 * ((R)2 + e1));
         p.u = w * p.u + amp * noise;                                 // O at X_{n+1/2}
@@ -297,6 +338,38 @@ __device__ __forceinline__ void init_path(const Consts<R>& c, Path<R>& p, R x0, 
     if (INTEG == KINTEG_BAOAB) drift_at<R, PROF>(c, x0, p.a, p.b);
 }
 
+// The time loop of one sample: M_l fine steps and, on levels >= 1, M_l / 2 coarse
+// steps driven by the combined fine noise. SMALL applies to both paths.
+template <typename R, int INTEG, int PROF, bool SMALL>
+__device__ __forceinline__ void run_paths(const Consts<R>& c, const Stream& st, int level,
+                                          uint32_t M, R h, R hh, R h2, Path<R>& f, Path<R>& g) {
+    R tilde_a, tilde_b, w_a, w_b, z0, z1;
+    if (level == 0) {
+        for (uint32_t m = 0; m < M / 2; ++m) {
+            Normals<R>::pair(philox(st, m), z0, z1);
+            step<R, INTEG, PROF, false, SMALL>(c, f, h, hh, z0, tilde_a, w_a);
+            step<R, INTEG, PROF, false, SMALL>(c, f, h, hh, z1, tilde_b, w_b);
+        }
+        if (M & 1u) {
+            Normals<R>::pair(philox(st, M / 2), z0, z1);
+            step<R, INTEG, PROF, false, SMALL>(c, f, h, hh, z0, tilde_a, w_a);
+        }
+        return;
+    }
+    for (uint32_t m = 0; m < M / 2; ++m) {
+        Normals<R>::pair(philox(st, m), z0, z1);
+        step<R, INTEG, PROF, false, SMALL>(c, f, h, hh, z0, tilde_a, w_a);   // fine step 2m
+        step<R, INTEG, PROF, false, SMALL>(c, f, h, hh, z1, tilde_b, w_b);   // fine step 2m+1
+        R xi_c;
+        if (INTEG == KINTEG_SE)
+            xi_c = (tilde_a + tilde_b) * (R)0.70710678118654752440;  // Eq. (18)
+        else
+            xi_c = (w_a * tilde_a + tilde_b) * Math<R>::rsqrt(w_a * w_a + (R)1);   // Eq. (19)
+        R unused_t, unused_w;
+        step<R, INTEG, PROF, true, SMALL>(c, g, h2, h, xi_c, unused_t, unused_w);
+    }
+}
+
 // Runs one sample of `level`. Returns the terminal fine and coarse states.
 template <typename R, int INTEG, int PROF>
 __device__ __forceinline__ void run_sample(const KProblem& kp, const Consts<R>& c, int level,
@@ -309,31 +382,11 @@ __device__ __forceinline__ void run_sample(const KProblem& kp, const Consts<R>& 
     const uint32_t M = (uint32_t)kp.M0 << level;                 // M_l = M_0 2^l
     const double hd = kp.T / (double)M;                           // h_l = T / M_l
     const R h = (R)hd, hh = (R)(0.5 * hd), h2 = (R)(2.0 * hd);
-    R tilde_a, tilde_b, w_a, w_b, z0, z1;
-    if (level == 0) {
-        for (uint32_t m = 0; m < M / 2; ++m) {
-            Normals<R>::pair(philox(st, m), z0, z1);
-            step<R, INTEG, PROF, false>(c, f, h, hh, z0, tilde_a, w_a);
-            step<R, INTEG, PROF, false>(c, f, h, hh, z1, tilde_b, w_b);
-        }
-        if (M & 1u) {
-            Normals<R>::pair(philox(st, M / 2), z0, z1);
-            step<R, INTEG, PROF, false>(c, f, h, hh, z0, tilde_a, w_a);
-        }
-        return;
-    }
-    for (uint32_t m = 0; m < M / 2; ++m) {
-        Normals<R>::pair(philox(st, m), z0, z1);
-        step<R, INTEG, PROF, false>(c, f, h, hh, z0, tilde_a, w_a);   // fine step 2m
-        step<R, INTEG, PROF, false>(c, f, h, hh, z1, tilde_b, w_b);   // fine step 2m+1
-        R xi_c;
-        if (INTEG == KINTEG_SE)
-            xi_c = (tilde_a + tilde_b) * (R)0.70710678118654752440;  // Eq. (18)
-        else
-            xi_c = (w_a * tilde_a + tilde_b) * Math<R>::rsqrt(w_a * w_a + (R)1);   // Eq. (19)
-        R unused_t, unused_w;
-        step<R, INTEG, PROF, true>(c, g, h2, h, xi_c, unused_t, unused_w);
-    }
+    // the coarse step 2h decides on levels >= 1 (a short series there holds for h too)
+    if (small_steps<R>(kp, level == 0 ? hd : 2.0 * hd))
+        run_paths<R, INTEG, PROF, true>(c, st, level, M, h, hh, h2, f, g);
+    else
+        run_paths<R, INTEG, PROF, false>(c, st, level, M, h, hh, h2, f, g);
 }
 
 // Quantity of interest in FP64 (Sec. 2, Sec. 5).

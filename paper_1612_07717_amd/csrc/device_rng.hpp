@@ -50,10 +50,11 @@ __device__ __forceinline__ Words philox(const Stream& s, uint32_t block) {
     uint32_t k0 = s.k0, k1 = s.k1;
 #pragma unroll
     for (int round = 0; round < 10; ++round) {
-        // S-box: two 32x32 -> 64-bit products; high halves mixed with the other words
-        // and the round key, low halves passed on.
-        const uint32_t lo0 = kPhiloxM0 * x0, hi0 = __umulhi(kPhiloxM0, x0);
-        const uint32_t lo1 = kPhiloxM1 * x2, hi1 = __umulhi(kPhiloxM1, x2);
+        // S-box: two 32x32 -> 64-bit products (one v_mad_u64_u32 each); high halves
+        // mixed with the other words and the round key, low halves passed on.
+        const uint64_t p0 = (uint64_t)kPhiloxM0 * x0, p1 = (uint64_t)kPhiloxM1 * x2;
+        const uint32_t lo0 = (uint32_t)p0, hi0 = (uint32_t)(p0 >> 32);
+        const uint32_t lo1 = (uint32_t)p1, hi1 = (uint32_t)(p1 >> 32);
         const uint32_t y0 = hi1 ^ x1 ^ k0;
         const uint32_t y2 = hi0 ^ x3 ^ k1;
         x0 = y0;

@@ -72,7 +72,7 @@ struct ld_engine {
     KRange* h_ranges = nullptr;
     KTile* h_tiles = nullptr;
     ld_level_sums* h_running = nullptr;
-    hipGraphExec_t graph = nullptr;
+    hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};   // by profile mask
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::vector<Query> q;        // by slot
     int64_t next_handle = 0;
@@ -105,7 +105,8 @@ int validate_query(const ld_query* qq) {
 namespace {
 
 void release_resources(ld_engine* e) {
-    if (e->graph) (void)hipGraphExecDestroy(e->graph);
+    for (hipGraphExec_t g : e->graph)
+        if (g) (void)hipGraphExecDestroy(g);
     if (e->ev0) (void)hipEventDestroy(e->ev0);
     if (e->ev1) (void)hipEventDestroy(e->ev1);
     if (e->d_base) (void)hipFree(e->d_base);
@@ -158,11 +159,13 @@ uint64_t tiles_of_range(const ld_engine* e, const Query& qu, int32_t level, uint
     return (n + per * spl - 1) / (per * spl);
 }
 
-int capture_graph(ld_engine* e) {
+// One graph per set of profiles present (the persistent kernel of a profile without
+// tiles is left out rather than launched empty).
+int capture_graph(ld_engine* e, uint32_t mask) {
     hipGraph_t g = nullptr;
     if (hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return fail(LD_EDEVICE, "hipStreamBeginCapture failed");
-    int rc = launch_engine_iteration(e->opts.precision, e->grid, e->d_hdr, e->d_tiles, e->d_problems,
+    int rc = launch_engine_iteration(e->opts.precision, e->grid, mask, e->d_hdr, e->d_tiles, e->d_problems,
                                      e->d_partials, e->d_counters, e->d_ranges, e->d_running,
                                      e->d_range_out, e->stream);
     const hipError_t ec = hipStreamEndCapture(e->stream, &g);
@@ -170,7 +173,7 @@ int capture_graph(ld_engine* e) {
         if (g) (void)hipGraphDestroy(g);
         return fail(LD_EDEVICE, "graph capture failed");
     }
-    const hipError_t ei = hipGraphInstantiate(&e->graph, g, nullptr, nullptr, 0);
+    const hipError_t ei = hipGraphInstantiate(&e->graph[mask], g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (ei != hipSuccess) return fail(LD_EDEVICE, "hipGraphInstantiate failed");
     return LD_OK;
@@ -415,15 +418,17 @@ int ld_engine_step(ld_engine* e, int32_t* n_active) {
         hipMemcpyAsync(e->d_tiles, all.data(), all.size() * sizeof(KTile), hipMemcpyHostToDevice, e->stream) !=
             hipSuccess)
         return fail(LD_EDEVICE, "uploading the tile tables failed");
-    if (e->opts.use_graph && e->graph == nullptr) {
-        int rc = capture_graph(e);
+    const uint32_t mask = (n1 > 0 ? 1u << KPROFILE_NEUTRAL : 0u) | (n0 > 0 ? 1u << KPROFILE_HOMOGENEOUS : 0u);
+    if (e->opts.use_graph && e->graph[mask] == nullptr) {
+        int rc = capture_graph(e, mask);
         if (rc != LD_OK) return rc;
     }
     (void)hipEventRecord(e->ev0, e->stream);
     if (e->opts.use_graph) {
-        if (hipGraphLaunch(e->graph, e->stream) != hipSuccess) return fail(LD_EDEVICE, "hipGraphLaunch failed");
+        if (hipGraphLaunch(e->graph[mask], e->stream) != hipSuccess)
+            return fail(LD_EDEVICE, "hipGraphLaunch failed");
     } else {
-        int rc = launch_engine_iteration(e->opts.precision, e->grid, e->d_hdr, e->d_tiles, e->d_problems,
+        int rc = launch_engine_iteration(e->opts.precision, e->grid, mask, e->d_hdr, e->d_tiles, e->d_problems,
                                          e->d_partials, e->d_counters, e->d_ranges, e->d_running,
                                          e->d_range_out, e->stream);
         if (rc != LD_OK) return fail(rc, "engine launch failed");

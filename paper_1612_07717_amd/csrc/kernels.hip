@@ -182,13 +182,53 @@ struct PipeLds {
     int end_bad[64];
 };
 
+// Fine wave of a wave-specialised block: K fine step pairs of one chunk (fine steps
+// 2m, 2m + 1 for m = m0 .. m0 + K - 1 below P), reading the normals of buffer b and
+// publishing S xi of both steps and w of the first for the coarse wave.
+template <typename R, int INTEG, int PROF, bool SMALL>
+__device__ __forceinline__ void pipe_fine_chunk(const Consts<R>& c, Path<R>& p, R h, R hh,
+                                                PipeLds<R>& L, uint32_t b, uint32_t m0,
+                                                uint32_t P, int lane) {
+    for (int j = 0; j < kPipeChunk; ++j) {
+        if (m0 + j < P) {
+            R ta, tb, wa, wb;
+            step<R, INTEG, PROF, false, SMALL>(c, p, h, hh, L.nrm[b][j][0][lane], ta, wa);
+            step<R, INTEG, PROF, false, SMALL>(c, p, h, hh, L.nrm[b][j][1][lane], tb, wb);
+            L.msg[b][j][0][lane] = ta;
+            L.msg[b][j][1][lane] = tb;
+            L.msg[b][j][2][lane] = wa;
+        }
+    }
+}
+
+// Coarse wave: the K coarse steps of one chunk, each driven by the combined noise of
+// its fine pair (Eq. 18 for SE, Eq. 19 otherwise).
+template <typename R, int INTEG, int PROF, bool SMALL>
+__device__ __forceinline__ void pipe_coarse_chunk(const Consts<R>& c, Path<R>& p, R h2, R h,
+                                                  PipeLds<R>& L, uint32_t b, uint32_t m0,
+                                                  uint32_t P, int lane) {
+    for (int j = 0; j < kPipeChunk; ++j) {
+        if (m0 + j < P) {
+            const R ta = L.msg[b][j][0][lane], tb = L.msg[b][j][1][lane];
+            R xi_c;
+            if (INTEG == KINTEG_SE) {
+                xi_c = (ta + tb) * (R)0.70710678118654752440;             // Eq. (18)
+            } else {
+                const R wa = L.msg[b][j][2][lane];
+                xi_c = (wa * ta + tb) * Math<R>::rsqrt(wa * wa + (R)1);  // Eq. (19)
+            }
+            R unused_t, unused_w;
+            step<R, INTEG, PROF, true, SMALL>(c, p, h2, h, xi_c, unused_t, unused_w);
+        }
+    }
+}
+
 template <typename R, int INTEG, int PROF>
 __device__ __forceinline__ void pipe_samples(const KProblem& kp, const Consts<R>& c,
                                              const KItem& item, uint32_t local_block, Acc& acc,
                                              double* dump, PipeLds<R>& L) {
     constexpr int K = kPipeChunk;
     auto& nrm = L.nrm;
-    auto& msg = L.msg;
     auto& end_pc = L.end_pc;
     auto& end_bad = L.end_bad;
     const int wave = (int)wave_index(), lane = threadIdx.x & 63;   // roles: scalar branches
@@ -200,6 +240,7 @@ __device__ __forceinline__ void pipe_samples(const KProblem& kp, const Consts<R>
     const uint32_t nch = (P + K - 1) / K;
     const double hd = kp.T / (double)M;
     const R h = (R)hd, hh = (R)(0.5 * hd), h2 = (R)(2.0 * hd);
+    const bool small_f = small_steps<R>(kp, hd), small_c = small_steps<R>(kp, 2.0 * hd);
     const Stream st = make_stream(kp.seed, kp.stream_id, level, item.sample_begin + local);
     Path<R> p;
     if (wave >= 2) {
@@ -225,36 +266,18 @@ __device__ __forceinline__ void pipe_samples(const KProblem& kp, const Consts<R>
         } else if (wave == 2) {
             if (s >= 1 && s <= nch) {
                 const uint32_t b = (s - 1) & 1;
-                for (int j = 0; j < K; ++j) {
-                    const uint32_t m = (s - 1) * K + j;
-                    if (m < P) {
-                        R ta, tb, wa, wb;
-                        step<R, INTEG, PROF, false>(c, p, h, hh, nrm[b][j][0][lane], ta, wa);
-                        step<R, INTEG, PROF, false>(c, p, h, hh, nrm[b][j][1][lane], tb, wb);
-                        msg[b][j][0][lane] = ta;
-                        msg[b][j][1][lane] = tb;
-                        msg[b][j][2][lane] = wa;
-                    }
-                }
+                if (small_f)
+                    pipe_fine_chunk<R, INTEG, PROF, true>(c, p, h, hh, L, b, (s - 1) * K, P, lane);
+                else
+                    pipe_fine_chunk<R, INTEG, PROF, false>(c, p, h, hh, L, b, (s - 1) * K, P, lane);
             }
         } else {
             if (s >= 2) {
                 const uint32_t b = s & 1;   // == (s - 2) & 1
-                for (int j = 0; j < K; ++j) {
-                    const uint32_t m = (s - 2) * K + j;
-                    if (m < P) {
-                        const R ta = msg[b][j][0][lane], tb = msg[b][j][1][lane];
-                        R xi_c;
-                        if (INTEG == KINTEG_SE) {
-                            xi_c = (ta + tb) * (R)0.70710678118654752440;             // Eq. (18)
-                        } else {
-                            const R wa = msg[b][j][2][lane];
-                            xi_c = (wa * ta + tb) * Math<R>::rsqrt(wa * wa + (R)1);  // Eq. (19)
-                        }
-                        R unused_t, unused_w;
-                        step<R, INTEG, PROF, true>(c, p, h2, h, xi_c, unused_t, unused_w);
-                    }
-                }
+                if (small_c)
+                    pipe_coarse_chunk<R, INTEG, PROF, true>(c, p, h2, h, L, b, (s - 2) * K, P, lane);
+                else
+                    pipe_coarse_chunk<R, INTEG, PROF, false>(c, p, h2, h, L, b, (s - 2) * K, P, lane);
             }
         }
         __syncthreads();
@@ -315,8 +338,10 @@ __device__ __forceinline__ void run_block(const KProblem& kp, const KItem& item,
 
 // One kernel per (path precision, integrator, profile): all items of a launch share the
 // problem, so the choice is made on the host and each kernel holds two path bodies only.
+// At least 3 waves per SIMD (HIP's second bound): the FP64 bodies fit 168 registers
+// without spilling; the FP32 bodies use far fewer.
 template <typename R, int INTEG, int PROF>
-__global__ __launch_bounds__(kBlock) void level_kernel(const KArgs args,
+__global__ __launch_bounds__(kBlock, 3) void level_kernel(const KArgs args,
                                                        ld_level_sums* __restrict__ partials,
                                                        double* __restrict__ dump) {
     const uint32_t b = blockIdx.x;
@@ -489,23 +514,29 @@ int launch_levels(const KArgs& args, uint32_t total_blocks, ld_level_sums* d_par
     return LD_OK;
 }
 
-int launch_engine_iteration(int precision, uint32_t grid_blocks, const KHeader* d_hdr,
-                            const KTile* d_tiles, const KProblem* d_problems,
+int launch_engine_iteration(int precision, uint32_t grid_blocks, uint32_t profile_mask,
+                            const KHeader* d_hdr, const KTile* d_tiles, const KProblem* d_problems,
                             ld_level_sums* d_partials, uint32_t* d_counters,
                             const KRange* d_ranges, ld_level_sums* d_running,
                             ld_level_sums* d_range_out, void* stream) {
     hipStream_t s = (hipStream_t)stream;
+    const bool neutral = (profile_mask >> KPROFILE_NEUTRAL) & 1u;
+    const bool homogeneous = (profile_mask >> KPROFILE_HOMOGENEOUS) & 1u;
     hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, d_counters, 2);
     if (precision == LD_FP32) {
-        hipLaunchKernelGGL((persistent_kernel<float, KPROFILE_NEUTRAL>), dim3(grid_blocks), dim3(kBlock), 0, s,
-                           d_hdr, d_tiles, d_problems, d_partials, d_counters);
-        hipLaunchKernelGGL((persistent_kernel<float, KPROFILE_HOMOGENEOUS>), dim3(grid_blocks), dim3(kBlock), 0, s,
-                           d_hdr, d_tiles, d_problems, d_partials, d_counters);
+        if (neutral)
+            hipLaunchKernelGGL((persistent_kernel<float, KPROFILE_NEUTRAL>), dim3(grid_blocks), dim3(kBlock), 0,
+                               s, d_hdr, d_tiles, d_problems, d_partials, d_counters);
+        if (homogeneous)
+            hipLaunchKernelGGL((persistent_kernel<float, KPROFILE_HOMOGENEOUS>), dim3(grid_blocks), dim3(kBlock),
+                               0, s, d_hdr, d_tiles, d_problems, d_partials, d_counters);
     } else {
-        hipLaunchKernelGGL((persistent_kernel<double, KPROFILE_NEUTRAL>), dim3(grid_blocks), dim3(kBlock), 0, s,
-                           d_hdr, d_tiles, d_problems, d_partials, d_counters);
-        hipLaunchKernelGGL((persistent_kernel<double, KPROFILE_HOMOGENEOUS>), dim3(grid_blocks), dim3(kBlock), 0, s,
-                           d_hdr, d_tiles, d_problems, d_partials, d_counters);
+        if (neutral)
+            hipLaunchKernelGGL((persistent_kernel<double, KPROFILE_NEUTRAL>), dim3(grid_blocks), dim3(kBlock), 0,
+                               s, d_hdr, d_tiles, d_problems, d_partials, d_counters);
+        if (homogeneous)
+            hipLaunchKernelGGL((persistent_kernel<double, KPROFILE_HOMOGENEOUS>), dim3(grid_blocks), dim3(kBlock),
+                               0, s, d_hdr, d_tiles, d_problems, d_partials, d_counters);
     }
     hipLaunchKernelGGL(merge_ranges_kernel, dim3(kMergeGrid), dim3(kBlock), 0, s, d_hdr, d_ranges, d_partials,
                        d_running, d_range_out);

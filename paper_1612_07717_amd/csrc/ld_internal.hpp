@@ -31,6 +31,7 @@ constexpr uint32_t kPipeMinSteps = 256;           // shorter paths are not laten
 struct KProblem {
     double H, eps_reg, ks, kappa_tau, sigma_u, tau, T;
     double z0, w0, su_z0;          // release; su_z0 = regularised sigma_U(z0)
+    double lam_max;                // max of lambda = 1/tau over [0, H]
     double qa, qb, inv_delta;
     double coef[kMaxCoef];
     int32_t integ, profile, release, qoi_kind, r, ncoef, M0;
@@ -102,10 +103,11 @@ struct KRange {
 
 constexpr int kMergeGrid = 256;   // blocks of the range-merge kernel (grid-stride)
 
-// Enqueues one engine iteration: reset the queue counters, the persistent kernels of
-// both profiles, then the range merge into the running sums.
-int launch_engine_iteration(int precision, uint32_t grid_blocks, const KHeader* d_hdr,
-                            const KTile* d_tiles, const KProblem* d_problems,
+// Enqueues one engine iteration: reset the queue counters, the persistent kernel of
+// each profile whose bit (1 << KPROFILE_*) is set in profile_mask, then the range
+// merge into the running sums.
+int launch_engine_iteration(int precision, uint32_t grid_blocks, uint32_t profile_mask,
+                            const KHeader* d_hdr, const KTile* d_tiles, const KProblem* d_problems,
                             ld_level_sums* d_partials, uint32_t* d_counters,
                             const KRange* d_ranges, ld_level_sums* d_running,
                             ld_level_sums* d_range_out, void* stream);

@@ -115,3 +115,18 @@ def test_autotuner_returns_a_valid_configuration():
     assert d["blocks_per_cu"] in (2, 4, 6, 8, 12, 16) and t > 0
     res = ld.estimate_batch(qs, opts=best)
     assert all(r["status"] == 1 for r in res)
+
+
+def test_mixed_profiles_batch_equals_single():
+    """Queries of both turbulence profiles in one engine (both persistent kernels run),
+    and a batch of homogeneous queries only (the neutral kernel is left out)."""
+    cfgs = [(W.homogeneous(), 2e-2), (W.neutral(400.0, "GL"), 1e-2),
+            (W.homogeneous(z0=300.0, integrator="BAOAB"), 2e-2), (W.neutral(650.0, "BAOAB"), 1e-2)]
+    qs = [ld.make_query(c, e, N_init=2000, L_max=8) for c, e in cfgs]
+    mixed = ld.estimate_batch(qs, precision="fp32")
+    homog = ld.estimate_batch([qs[0], qs[2]], precision="fp32")
+    for (c, e), m in zip(cfgs, mixed):
+        s = ld.estimate(e, c, precision="fp32", eps_is_relative=True, N_init=2000, L_max=8)
+        say(f"{c['profile']} {c['integrator']}: {m['estimate']:.6f} N={m['N']}")
+        assert m["N"] == s["N"] and m["estimate"] == s["estimate"]
+    assert homog[0]["estimate"] == mixed[0]["estimate"] and homog[1]["estimate"] == mixed[2]["estimate"]
