@@ -99,6 +99,8 @@ int make_kproblem(const ld_problem* p, ld_integrator integ, KProblem* kp) {
         kp->kappa_tau = f.kappa_tau;
         kp->sigma_u = 1.0;   // unused
         kp->tau = 1.0;       // unused
+        kp->ksH = kp->ks * std::pow(f.H, -0.75);
+        kp->kl = kp->ksH / f.kappa_tau;
     } else {
         kp->eps_reg = 0.0;
         kp->ks = 0.0;

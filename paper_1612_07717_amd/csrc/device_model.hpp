@@ -125,15 +125,13 @@ struct Math<double> {
 
 };
 
-// Per-(problem, level) constants in the path precision.
+// Per-problem constants in the path precision.
 template <typename R>
 struct Consts {
-    R H, invH, eps, Hme;        // domain and cut-off heights
-    R sqrt_invH;                // H^(-1/2)
-    R ks;                       // kappa_sigma u_*
-    R acoef;                    // (3/4) (kappa_sigma u_*)^2 / H
+    R H, eps, Hme;              // domain and cut-off heights
+    R ksH;                      // kappa_sigma u_* H^(-3/4): sigma_U = ksH (H - X)^(3/4)
+    R kl;                       // ksH / kappa_tau: lambda = kl (H - X)^(3/4) / X
     R acoef_h;                  // (3/4) (kappa_sigma u_*)^2 / H^(3/2)
-    R inv_kt;                   // 1 / kappa_tau
     R su_h, lam_h;              // homogeneous sigma_U and lambda
 };
 
@@ -141,40 +139,48 @@ template <typename R>
 __device__ __forceinline__ Consts<R> make_consts(const KProblem& p) {
     Consts<R> c;
     c.H = (R)p.H;
-    c.invH = (R)(1.0 / p.H);
-    c.sqrt_invH = (R)(1.0 / sqrt(p.H));
     c.eps = (R)p.eps_reg;
     c.Hme = (R)(p.H - p.eps_reg);
-    c.ks = (R)p.ks;
-    c.acoef = (R)(0.75 * p.ks * p.ks / p.H);
+    c.ksH = (R)p.ksH;
+    c.kl = (R)p.kl;
     c.acoef_h = (R)(0.75 * p.ks * p.ks / (p.H * sqrt(p.H)));
-    c.inv_kt = (R)(1.0 / p.kappa_tau);
     c.su_h = (R)p.sigma_u;
     c.lam_h = (R)(1.0 / p.tau);
     return c;
 }
 
-// sigma_U and lambda at X (Eqs. 5, 7).
+// sigma_U at X (Eqs. 5, 7): kappa_sigma u_* (1 - X_c/H)^(3/4) with X_c the cut-off X.
 template <typename R, int PROF>
-__device__ __forceinline__ void profile_at(const Consts<R>& c, R x, R& su, R& lam) {
+__device__ __forceinline__ R sigma_at(const Consts<R>& c, R x) {
+    if (PROF == KPROFILE_HOMOGENEOUS) return c.su_h;
+    const R d = c.H - Math<R>::clamp_(x, c.eps, c.Hme);
+    return c.ksH * Math<R>::sqrt_(d * Math<R>::sqrt_(d));
+}
+
+// O-step coefficients at X for step size h: sigma_U and z = -lambda h, lambda = 1/tau =
+// sigma_U / (kappa_tau X_c) (Eqs. 5, 7). With r = (H - X_c)^(3/4) both are one multiply
+// from r: sigma_U = ksH r, z = r (-kl h / X_c); -kl h is the same for every step of a
+// path and 1/X_c is computed beside r.
+template <typename R, int PROF>
+__device__ __forceinline__ void o_coeffs(const Consts<R>& c, R x, R h, R& su, R& z) {
     if (PROF == KPROFILE_HOMOGENEOUS) {
         su = c.su_h;
-        lam = c.lam_h;
+        z = -c.lam_h * h;
     } else {
         const R xc = Math<R>::clamp_(x, c.eps, c.Hme);
-        const R s = (c.H - xc) * c.invH;
-        const R sq = Math<R>::sqrt_(s);
-        su = c.ks * Math<R>::sqrt_(s * sq);           // kappa_sigma u_* s^(3/4)
-        lam = su * c.inv_kt * Math<R>::rcp(xc);        // sigma_U / (kappa_tau X)
+        const R d = c.H - xc;
+        const R r = Math<R>::sqrt_(d * Math<R>::sqrt_(d));
+        su = c.ksH * r;
+        z = r * ((-c.kl * h) * Math<R>::rcp(xc));
     }
 }
 
-// sigma_U, lambda and the drift coefficients a, b at X.
+// o_coeffs and the drift coefficients a, b at X (one square root of H - X_c serves both).
 template <typename R, int PROF>
-__device__ __forceinline__ void coeffs_at(const Consts<R>& c, R x, R& su, R& lam, R& a, R& b) {
+__device__ __forceinline__ void coeffs_at(const Consts<R>& c, R x, R h, R& su, R& z, R& a, R& b) {
     if (PROF == KPROFILE_HOMOGENEOUS) {
         su = c.su_h;
-        lam = c.lam_h;
+        z = -c.lam_h * h;
         a = (R)0;
         b = (R)0;
     } else {
@@ -182,10 +188,9 @@ __device__ __forceinline__ void coeffs_at(const Consts<R>& c, R x, R& su, R& lam
         const R d = c.H - xc;
         R sqd, invd;
         Math<R>::sqrt_and_rcp(d, sqd, invd);
-        const R s = d * c.invH;
-        const R sq = sqd * c.sqrt_invH;                     // sqrt(1 - X/H)
-        su = c.ks * Math<R>::sqrt_(s * sq);
-        lam = su * c.inv_kt * Math<R>::rcp(xc);
+        const R r = Math<R>::sqrt_(d * sqd);
+        su = c.ksH * r;
+        z = r * ((-c.kl * h) * Math<R>::rcp(xc));
         const bool inside = (x >= c.eps) && (x <= c.Hme);   // then xc == x
         a = inside ? c.acoef_h * sqd : (R)0;
         b = inside ? (R)0.75 * invd : (R)0;
@@ -260,22 +265,22 @@ template <typename R, int INTEG, int PROF, bool COARSE, bool SMALL>
 __device__ __forceinline__ void step(const Consts<R>& c, Path<R>& p, R h, R hh, R xi,
                                      R& tilde, R& w) {
     if (INTEG == KINTEG_SE) {                                        // Eq. (8)
-        R su, lam, a, b;
-        coeffs_at<R, PROF>(c, p.x, su, lam, a, b);
+        R su, z, a, b;                                               // z = -lambda h
+        coeffs_at<R, PROF>(c, p.x, h, su, z, a, b);
         const R noise = COARSE ? Math<R>::flip(xi, p.sgn) : xi;
         if (!COARSE) tilde = Math<R>::flip(xi, p.sgn);
-        const R amp = su * Math<R>::sqrt_((R)2 * lam * h);             // sigma sqrt(h)
+        const R amp = su * Math<R>::sqrt_((R)-2 * z);                  // sigma sqrt(h)
         const R drift = -(a + b * p.u * p.u);
-        p.u = ((R)1 - lam * h) * p.u + drift * h + amp * noise;
+        p.u = ((R)1 + z) * p.u + drift * h + amp * noise;
         p.x = p.x + p.u * h;
         fold(p, c.H);
         w = (R)1;
     } else if (INTEG == KINTEG_GL) {                                 // Eq. (9)
-        R su, lam, a, b;
-        coeffs_at<R, PROF>(c, p.x, su, lam, a, b);
+        R su, z, a, b;
+        coeffs_at<R, PROF>(c, p.x, h, su, z, a, b);
         const R noise = COARSE ? Math<R>::flip(xi, p.sgn) : xi;
         if (!COARSE) tilde = Math<R>::flip(xi, p.sgn);
-        const R e1 = o_step_expm1<R, SMALL>(-lam * h);
+        const R e1 = o_step_expm1<R, SMALL>(z);
         w = (R)1 + e1;
         const R amp = su * Math<R>::sqrt_(-e1 * ((R)2 + e1));
         const R us = w * p.u + amp * noise;                          // O
@@ -286,11 +291,11 @@ __device__ __forceinline__ void step(const Consts<R>& c, Path<R>& p, R h, R hh, 
         p.u = p.u - (p.a + p.b * p.u * p.u) * hh;                    // B at (X_n, U_n)
         p.x = p.x + p.u * hh;                                        // A
         fold(p, c.H);
-        R su, lam;
-        profile_at<R, PROF>(c, p.x, su, lam);
+        R su, z;
+        o_coeffs<R, PROF>(c, p.x, h, su, z);
         const R noise = COARSE ? Math<R>::flip(xi, p.sgn) : xi;
         if (!COARSE) tilde = Math<R>::flip(xi, p.sgn);
-        const R e1 = o_step_expm1<R, SMALL>(-lam * h);
+        const R e1 = o_step_expm1<R, SMALL>(z);
         w = (R)1 + e1;
         const R amp = su * Math<R>::sqrt_(-e1 * ((R)2 + e1));
         p.u = w * p.u + amp * noise;                                 // O at X_{n+1/2}
@@ -322,9 +327,7 @@ __device__ __forceinline__ void initial_state(const KProblem& kp, const Consts<R
         x0 = (R)(kp.H * uniform64(wx.r1, wx.r0));
     else
         x0 = (R)kp.H * (R)uniform32(wx.r1);
-    R su, lam;
-    profile_at<R, PROF>(c, x0, su, lam);
-    u0 = su * z0;
+    u0 = sigma_at<R, PROF>(c, x0) * z0;
 }
 
 template <typename R, int INTEG, int PROF>

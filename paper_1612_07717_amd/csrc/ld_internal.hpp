@@ -32,6 +32,7 @@ struct KProblem {
     double H, eps_reg, ks, kappa_tau, sigma_u, tau, T;
     double z0, w0, su_z0;          // release; su_z0 = regularised sigma_U(z0)
     double lam_max;                // max of lambda = 1/tau over [0, H]
+    double ksH, kl;                // kappa_sigma u_* H^(-3/4) and ksH / kappa_tau
     double qa, qb, inv_delta;
     double coef[kMaxCoef];
     int32_t integ, profile, release, qoi_kind, r, ncoef, M0;
