@@ -96,6 +96,33 @@ class Result(C.Structure):
 _lib = None
 
 
+MAX_LEVELS, MAX_BINS = 32, 64
+MLMC, STMC = 0, 1
+
+
+class PdfPlanIn(C.Structure):
+    _fields_ = [("L", C.c_int32), ("n_bins", C.c_int32), ("n", C.c_uint64 * MAX_LEVELS),
+                ("sum1", (C.c_double * MAX_BINS) * MAX_LEVELS),
+                ("sum2", (C.c_double * MAX_BINS) * MAX_LEVELS),
+                ("M0", C.c_int32), ("L_max", C.c_int32), ("eps", C.c_double),
+                ("fixed_L", C.c_int32), ("pad", C.c_int32), ("N_init", C.c_uint64),
+                ("alpha", C.c_double)]
+
+
+class PdfPlanOut(C.Structure):
+    _fields_ = [("status", C.c_int32), ("L", C.c_int32), ("dn", C.c_uint64 * MAX_LEVELS),
+                ("V", C.c_double * MAX_LEVELS), ("estimate", C.c_double * MAX_BINS),
+                ("bias_est", C.c_double), ("stat_var", C.c_double), ("alpha", C.c_double)]
+
+
+class PdfResult(C.Structure):
+    _fields_ = [("estimate", C.c_double * MAX_BINS), ("bias_est", C.c_double),
+                ("stat_var", C.c_double), ("rmse_est", C.c_double), ("L", C.c_int32),
+                ("iterations", C.c_int32), ("status", C.c_int32), ("estimator", C.c_int32),
+                ("N", C.c_uint64 * MAX_LEVELS), ("n_nonfinite", C.c_uint64),
+                ("V", C.c_double * MAX_LEVELS), ("fine_steps", C.c_double)]
+
+
 def load():
     """Load liboracle.so, building it first if it is missing."""
     global _lib
@@ -123,6 +150,13 @@ def load():
     lib.oracle_sums_value.restype = C.c_double
     lib.oracle_plan.argtypes = [P(PlanIn), P(PlanOut)]
     lib.oracle_estimate.argtypes = [C.c_double, P(Problem), P(Opts), P(Result)]
+    lib.oracle_pdf_level_sums.argtypes = [P(Problem), C.c_int32, C.c_uint64, C.c_uint64,
+                                          C.c_double, C.c_double, C.c_int32, P(Sums)]
+    lib.oracle_pdf_level_sums.restype = None
+    lib.oracle_pdf_plan.argtypes = [P(PdfPlanIn), P(PdfPlanOut)]
+    lib.oracle_pdf_plan.restype = None
+    lib.oracle_estimate_pdf.argtypes = [C.c_double, P(Problem), P(Opts), C.c_double, C.c_double,
+                                        C.c_int32, C.c_int32, P(PdfResult)]
     lib.oracle_num_threads.restype = C.c_int
     _lib = lib
     return lib
@@ -272,6 +306,48 @@ def estimate(eps, cfg, *, L_min=2, L_max=10, fixed_L=-1, fixed_N=False, N_init=1
             "N": [int(r.N[l]) for l in range(L + 1)], "n_nonfinite": int(r.n_nonfinite),
             "Yhat": list(r.Yhat[: L + 1]), "V": list(r.V[: L + 1]),
             "fine_steps": r.fine_steps, "integrator_steps": r.integrator_steps}
+
+
+def pdf_level_sums(cfg, level, begin, n, a0, width, n_bins) -> list:
+    """Per-bin sums of the binned concentration (Sec. 6.4), one dict per bin."""
+    out = (Sums * n_bins)()
+    load().oracle_pdf_level_sums(C.byref(make_problem(cfg)), level, begin, n, float(a0),
+                                 float(width), n_bins, out)
+    return [_sums_dict(s) for s in out]
+
+
+def pdf_plan(d: dict) -> dict:
+    """d: L, n_bins, n[l], sum1[l][i], sum2[l][i], M0, eps, L_max, fixed_L, N_init, alpha."""
+    pin = PdfPlanIn()
+    pin.L, pin.n_bins = d["L"], d["n_bins"]
+    for l in range(d["L"] + 1):
+        pin.n[l] = d["n"][l]
+        for i in range(d["n_bins"]):
+            pin.sum1[l][i] = d["sum1"][l][i]
+            pin.sum2[l][i] = d["sum2"][l][i]
+    pin.M0, pin.eps, pin.L_max = d["M0"], d["eps"], d.get("L_max", 20)
+    pin.fixed_L, pin.N_init, pin.alpha = d.get("fixed_L", -1), d.get("N_init", 10000), d.get("alpha", 1.0)
+    out = PdfPlanOut()
+    load().oracle_pdf_plan(C.byref(pin), C.byref(out))
+    L = out.L
+    return {"status": out.status, "L": L, "dn": [int(out.dn[l]) for l in range(L + 1)],
+            "V": list(out.V[: d["L"] + 1]), "estimate": list(out.estimate[: d["n_bins"]]),
+            "bias_est": out.bias_est, "stat_var": out.stat_var, "alpha": out.alpha}
+
+
+def estimate_pdf(eps, cfg, a0, width, n_bins, *, estimator=MLMC, L_min=2, L_max=10, fixed_L=-1,
+                 N_init=10000, max_iter=100, alpha=1.0) -> dict:
+    o = Opts(L_min=L_min, L_max=L_max, fixed_L=fixed_L, fixed_N=0, N_init=N_init,
+             eps_is_relative=0, max_iter=max_iter, alpha=alpha)
+    r = PdfResult()
+    rc = load().oracle_estimate_pdf(float(eps), C.byref(make_problem(cfg)), C.byref(o), float(a0),
+                                    float(width), n_bins, estimator, C.byref(r))
+    L = r.L
+    nl = 1 if estimator == STMC else L + 1
+    return {"rc": rc, "estimate": list(r.estimate[:n_bins]), "bias_est": r.bias_est,
+            "stat_var": r.stat_var, "rmse_est": r.rmse_est, "L": L, "iterations": r.iterations,
+            "status": r.status, "N": [int(r.N[l]) for l in range(nl)],
+            "n_nonfinite": int(r.n_nonfinite), "V": list(r.V[:nl]), "fine_steps": r.fine_steps}
 
 
 def num_threads() -> int:

@@ -680,6 +680,260 @@ int oracle_estimate(double eps, const oracle_problem* p, const oracle_opts* opts
     return out->n_nonfinite ? -5 : 0;
 }
 
+/* ================================================================================== */
+/* Vector QoI: the binned concentration of Sec. 6.4.                                  */
+/* ================================================================================== */
+
+void oracle_pdf_level_sums(const oracle_problem* p, int32_t level, uint64_t begin,
+                           uint64_t n, double a0, double width, int32_t n_bins,
+                           oracle_sums* out) {
+    /* one scalar context per bin: the box [a_i, a_{i+1}] of Eq. (34) / (37) */
+    context* box = (context*)malloc((size_t)n_bins * sizeof(context));
+    for (int32_t i = 0; i < n_bins; ++i) {
+        oracle_problem q = *p;
+        q.qoi_kind = ORACLE_QOI_P_BOX;
+        q.qa = a0 + (double)i * width;
+        q.qb = a0 + (double)(i + 1) * width;
+        make_context(&q, &box[i]);
+    }
+    context ctx;
+    make_context(p, &ctx);
+    uint64_t nchunks = (n + ORACLE_CHUNK - 1) / ORACLE_CHUNK;
+    oracle_sums* part = (oracle_sums*)calloc((nchunks ? nchunks : 1) * (size_t)n_bins,
+                                             sizeof(oracle_sums));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t ch = 0; ch < (int64_t)nchunks; ++ch) {
+        oracle_sums* acc = &part[(size_t)ch * n_bins];
+        uint64_t lo = (uint64_t)ch * ORACLE_CHUNK;
+        uint64_t hi = lo + ORACLE_CHUNK < n ? lo + ORACLE_CHUNK : n;
+        for (uint64_t k = lo; k < hi; ++k) {
+            double fine[3], coarse[3];
+            int bad = run_sample(&ctx, level, begin + k, fine, coarse);
+            if (bad || !isfinite(fine[0]) || (level != 0 && !isfinite(coarse[0]))) {
+                for (int32_t i = 0; i < n_bins; ++i) acc[i].n_nonfinite++;
+                continue;
+            }
+            for (int32_t i = 0; i < n_bins; ++i) {
+                double pf = qoi(&box[i], fine[0], fine[1]);
+                double pc = (level == 0) ? 0.0 : qoi(&box[i], coarse[0], coarse[1]);
+                double y = pf - pc;
+                neumaier_add(&acc[i].s[0], &acc[i].c[0], y);
+                neumaier_add(&acc[i].s[1], &acc[i].c[1], y * y);
+                neumaier_add(&acc[i].s[2], &acc[i].c[2], pf);
+                neumaier_add(&acc[i].s[3], &acc[i].c[3], pf * pf);
+                acc[i].n++;
+            }
+        }
+    }
+    for (int32_t i = 0; i < n_bins; ++i) {
+        memset(&out[i], 0, sizeof out[i]);
+        for (uint64_t ch = 0; ch < nchunks; ++ch) sums_merge(&out[i], &part[ch * n_bins + i]);
+    }
+    free(part);
+    free(box);
+}
+
+static void mean_var(uint64_t n_, double s1, double s2, double* mean, double* var) {
+    double n = (double)n_;
+    *mean = n_ > 0 ? s1 / n : 0.0;
+    *var = 0.0;
+    if (n_ > 1) *var = (s2 - n * *mean * *mean) / (n - 1.0);
+    if (!(*var > 0.0)) *var = 0.0;
+}
+
+void oracle_pdf_plan(const oracle_pdf_plan_in* in, oracle_pdf_plan_out* out) {
+    memset(out, 0, sizeof *out);
+    int32_t L = in->L, k = in->n_bins;
+    double Yhat[ORACLE_MAX_LEVELS][ORACLE_MAX_BINS];
+    double Ymax[ORACLE_MAX_LEVELS];
+    double stat_var = 0.0;
+    for (int32_t i = 0; i < k; ++i) out->estimate[i] = 0.0;
+    for (int32_t l = 0; l <= L; ++l) {
+        out->V[l] = 0.0;
+        Ymax[l] = 0.0;
+        for (int32_t i = 0; i < k; ++i) {
+            double mean, var;
+            mean_var(in->n[l], in->sum1[l][i], in->sum2[l][i], &mean, &var);
+            Yhat[l][i] = mean;
+            out->estimate[i] += mean;
+            if (var > out->V[l]) out->V[l] = var;           /* max_i Var[Y_{l,i}] */
+            if (fabs(mean) > Ymax[l]) Ymax[l] = fabs(mean);
+        }
+    }
+    for (int32_t i = 0; i < k; ++i) {                       /* max_i sum_l V_{l,i} / N_l */
+        double sv = 0.0;
+        for (int32_t l = 0; l <= L; ++l) {
+            double mean, var;
+            mean_var(in->n[l], in->sum1[l][i], in->sum2[l][i], &mean, &var);
+            if (in->n[l] > 0) sv += var / (double)in->n[l];
+        }
+        if (sv > stat_var) stat_var = sv;
+    }
+    out->stat_var = stat_var;
+    double alpha = in->alpha;
+    if (!(alpha > 0.0)) {                                   /* fit on max_i |Yhat_{l,i}| */
+        alpha = 1.0;
+        double sl = 0, sy = 0, sll = 0, sly = 0;
+        int cnt = 0;
+        for (int32_t l = 1; l <= L; ++l) {
+            if (!(Ymax[l] > 0.0)) continue;
+            double y = -log2(Ymax[l]);
+            sl += l; sy += y; sll += (double)l * l; sly += l * y;
+            cnt++;
+        }
+        if (cnt >= 2) {
+            double den = cnt * sll - sl * sl;
+            if (den > 0) alpha = (cnt * sly - sl * sy) / den;
+        }
+        if (!(alpha >= 0.5)) alpha = 0.5;
+        if (alpha > 2.0) alpha = 2.0;
+    }
+    out->alpha = alpha;
+    double bias = 0.0;
+    if (L >= 1) {
+        for (int32_t i = 0; i < k; ++i) {
+            double a = fabs(Yhat[L][i]);
+            double b = fabs(Yhat[L - 1][i]) / pow(2.0, alpha);
+            double bi = (a > b ? a : b) / (pow(2.0, alpha) - 1.0);
+            if (bi > bias) bias = bi;
+        }
+    }
+    out->bias_est = bias;
+    out->L = L;
+    /* the scalar decision with V_l = max_i Var[Y_{l,i}] */
+    oracle_plan_in sc;
+    memset(&sc, 0, sizeof sc);
+    sc.L = L;
+    sc.M0 = in->M0;
+    for (int32_t l = 0; l <= L; ++l) sc.n[l] = in->n[l];
+    optimal_dn(&sc, L, out->V, in->eps, out->dn);
+    int more = 0;
+    for (int32_t l = 0; l <= L; ++l)
+        if ((double)out->dn[l] > 0.01 * (double)in->n[l]) more = 1;
+    if (more) {
+        out->status = 0;
+        return;
+    }
+    for (int32_t l = 0; l <= L; ++l) out->dn[l] = 0;
+    if (in->fixed_L >= 0 || L < 1 || bias <= in->eps / sqrt(2.0)) {
+        out->status = 1;
+        return;
+    }
+    if (L >= in->L_max || L + 1 >= ORACLE_MAX_LEVELS) {
+        out->status = 2;
+        return;
+    }
+    double V[ORACLE_MAX_LEVELS];
+    for (int32_t l = 0; l <= L; ++l) V[l] = out->V[l];
+    V[L + 1] = V[L] / 4.0;
+    optimal_dn(&sc, L + 1, V, in->eps, out->dn);
+    if (out->dn[L + 1] < in->N_init) out->dn[L + 1] = in->N_init;
+    out->L = L + 1;
+    out->status = 0;
+}
+
+int oracle_estimate_pdf(double eps, const oracle_problem* p, const oracle_opts* opts,
+                        double a0, double width, int32_t n_bins, int32_t estimator,
+                        oracle_pdf_result* out) {
+    memset(out, 0, sizeof *out);
+    if (!(eps > 0.0) || n_bins < 1 || n_bins > ORACLE_MAX_BINS) return -1;
+    out->estimator = estimator;
+    int max_iter = opts->max_iter > 0 ? opts->max_iter : 100;
+    oracle_sums* sums = (oracle_sums*)calloc((size_t)ORACLE_MAX_LEVELS * n_bins, sizeof(oracle_sums));
+    oracle_sums* add = (oracle_sums*)calloc((size_t)n_bins, sizeof(oracle_sums));
+    uint64_t drawn[ORACLE_MAX_LEVELS];
+    memset(drawn, 0, sizeof drawn);
+    int iter = 0;
+    if (estimator == ORACLE_STMC) {
+        /* the single fine path of level L: level 0 of the problem with M0 2^L steps */
+        if (opts->fixed_L < 0) { free(sums); free(add); return -1; }
+        oracle_problem q = *p;
+        q.M0 = p->M0 << opts->fixed_L;
+        uint64_t dn = opts->N_init;
+        double V = 0.0;
+        for (;;) {
+            oracle_pdf_level_sums(&q, 0, drawn[0], dn, a0, width, n_bins, add);
+            for (int32_t i = 0; i < n_bins; ++i) sums_merge(&sums[i], &add[i]);
+            drawn[0] += dn;
+            ++iter;
+            uint64_t n = sums[0].n;
+            V = 0.0;
+            for (int32_t i = 0; i < n_bins; ++i) {
+                double mean, var;
+                mean_var(n, oracle_sums_value(&sums[i], 0), oracle_sums_value(&sums[i], 1), &mean, &var);
+                out->estimate[i] = mean;
+                if (var > V) V = var;
+            }
+            double target = ceil(2.0 * V / (eps * eps));
+            dn = (target > (double)n) ? (uint64_t)target - n : 0;
+            if (!((double)dn > 0.01 * (double)n) || iter >= max_iter) break;
+        }
+        out->L = opts->fixed_L;
+        out->N[0] = drawn[0];
+        out->V[0] = V;
+        out->stat_var = V / (double)(sums[0].n ? sums[0].n : 1);
+        out->rmse_est = sqrt(out->stat_var);
+        out->status = 1;
+        out->iterations = iter;
+        out->n_nonfinite = sums[0].n_nonfinite;
+        out->fine_steps = (double)drawn[0] * (double)q.M0;
+        free(sums);
+        free(add);
+        return out->n_nonfinite ? -5 : 0;
+    }
+    oracle_pdf_plan_in* in = (oracle_pdf_plan_in*)calloc(1, sizeof *in);
+    in->L = opts->fixed_L >= 0 ? opts->fixed_L : opts->L_min;
+    in->n_bins = n_bins;
+    in->M0 = p->M0;
+    in->eps = eps;
+    in->L_max = opts->L_max;
+    in->fixed_L = opts->fixed_L;
+    in->N_init = opts->N_init;
+    in->alpha = opts->alpha;
+    uint64_t dn[ORACLE_MAX_LEVELS];
+    memset(dn, 0, sizeof dn);
+    for (int32_t l = 0; l <= in->L; ++l) dn[l] = opts->N_init;
+    oracle_pdf_plan_out plan;
+    memset(&plan, 0, sizeof plan);
+    for (;;) {
+        for (int32_t l = 0; l <= in->L; ++l) {
+            if (dn[l] == 0) continue;
+            oracle_pdf_level_sums(p, l, drawn[l], dn[l], a0, width, n_bins, add);
+            for (int32_t i = 0; i < n_bins; ++i) sums_merge(&sums[(size_t)l * n_bins + i], &add[i]);
+            drawn[l] += dn[l];
+        }
+        for (int32_t l = 0; l <= in->L; ++l) {
+            in->n[l] = sums[(size_t)l * n_bins].n;
+            for (int32_t i = 0; i < n_bins; ++i) {
+                in->sum1[l][i] = oracle_sums_value(&sums[(size_t)l * n_bins + i], 0);
+                in->sum2[l][i] = oracle_sums_value(&sums[(size_t)l * n_bins + i], 1);
+            }
+        }
+        oracle_pdf_plan(in, &plan);
+        ++iter;
+        if (plan.status != 0 || iter >= max_iter) break;
+        in->L = plan.L;
+        memcpy(dn, plan.dn, sizeof dn);
+    }
+    for (int32_t i = 0; i < n_bins; ++i) out->estimate[i] = plan.estimate[i];
+    out->bias_est = plan.bias_est;
+    out->stat_var = plan.stat_var;
+    out->rmse_est = sqrt(plan.bias_est * plan.bias_est + plan.stat_var);
+    out->L = plan.L;
+    out->iterations = iter;
+    out->status = plan.status == 0 ? 2 : plan.status;
+    for (int32_t l = 0; l <= plan.L; ++l) {
+        out->N[l] = drawn[l];
+        out->n_nonfinite += sums[(size_t)l * n_bins].n_nonfinite;
+        out->V[l] = plan.V[l];
+        out->fine_steps += (double)drawn[l] * level_cost(p->M0, l);
+    }
+    free(in);
+    free(sums);
+    free(add);
+    return out->n_nonfinite ? -5 : 0;
+}
+
 int oracle_num_threads(void) {
 #ifdef _OPENMP
     return omp_get_max_threads();

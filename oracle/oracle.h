@@ -159,6 +159,64 @@ typedef struct {
 int oracle_estimate(double eps, const oracle_problem* p, const oracle_opts* opts,
                     oracle_result* out);
 
+/* ---- vector QoI: binned concentration (Sec. 6.4) --------------------------------- */
+#define ORACLE_MAX_BINS 64
+enum { ORACLE_MLMC = 0, ORACLE_STMC = 1 };
+
+/* Per-bin sums for the vector QoI of Sec. 6.4. Bin i is [a0 + i w, a0 + (i+1) w],
+   i < n_bins; P_i is the box indicator of Eq. (34) (r = 0) or its smoothing by Eq. (37)
+   (r > 0), with the problem's r and delta (its qoi_kind is ignored); Y_i = P_i(X_f) -
+   P_i(X_c) (Eq. 16; P_i(X_c) = 0 on level 0). out[i] for i < n_bins. A sample whose
+   paths are not finite is excluded from every bin and counted in each. */
+void oracle_pdf_level_sums(const oracle_problem* p, int32_t level, uint64_t begin,
+                           uint64_t n, double a0, double width, int32_t n_bins,
+                           oracle_sums* out);
+
+/* One decision of the adaptive algorithm for the vector QoI: the sample rule uses
+   max_i Var[Y_{l,i}] in place of Var[Y_l] (Sec. 6.4); the bias test takes, over the bins,
+   the largest of the scalar bias estimates; eps is absolute. */
+typedef struct {
+    int32_t L, n_bins;
+    uint64_t n[ORACLE_MAX_LEVELS];
+    double sum1[ORACLE_MAX_LEVELS][ORACLE_MAX_BINS];   /* sum of Y_{l,i} */
+    double sum2[ORACLE_MAX_LEVELS][ORACLE_MAX_BINS];   /* sum of Y_{l,i}^2 */
+    int32_t M0;
+    int32_t L_max;
+    double eps;
+    int32_t fixed_L;
+    int32_t pad;
+    uint64_t N_init;
+    double alpha;                                      /* <= 0: fit on max_i |Yhat_{l,i}| */
+} oracle_pdf_plan_in;
+
+typedef struct {
+    int32_t status, L;                                 /* as oracle_plan_out */
+    uint64_t dn[ORACLE_MAX_LEVELS];
+    double V[ORACLE_MAX_LEVELS];                       /* max_i Var[Y_{l,i}] */
+    double estimate[ORACLE_MAX_BINS];                  /* sum_l Yhat_{l,i} */
+    double bias_est, stat_var, alpha;                  /* maxima over the bins */
+} oracle_pdf_plan_out;
+
+void oracle_pdf_plan(const oracle_pdf_plan_in* in, oracle_pdf_plan_out* out);
+
+typedef struct {
+    double estimate[ORACLE_MAX_BINS];
+    double bias_est, stat_var, rmse_est;
+    int32_t L, iterations, status, estimator;
+    uint64_t N[ORACLE_MAX_LEVELS];
+    uint64_t n_nonfinite;
+    double V[ORACLE_MAX_LEVELS];
+    double fine_steps;
+} oracle_pdf_result;
+
+/* Binned-concentration estimate to absolute RMSE eps per bin. ORACLE_MLMC: the adaptive
+   driver with oracle_pdf_plan. ORACLE_STMC: standard Monte Carlo (Sec. 3.2) with the
+   single fine path of step T / (M0 2^L), L = opts->fixed_L (>= 0): N_init samples,
+   then N = ceil(2 max_i Var[P_i] / eps^2) with the same 1 % top-up rule. */
+int oracle_estimate_pdf(double eps, const oracle_problem* p, const oracle_opts* opts,
+                        double a0, double width, int32_t n_bins, int32_t estimator,
+                        oracle_pdf_result* out);
+
 int oracle_num_threads(void);
 
 #ifdef __cplusplus
