@@ -248,6 +248,85 @@ int mlmc_estimate(double eps, const ld_qoi* qoi, ld_integrator integrator,
                   const ld_profile* profile, const ld_estimate_opts* opts,
                   ld_estimate_result* out);
 
+/* ---- vector QoI: the binned concentration of Sec. 6.4 --------------------------- */
+
+#define LD_MAX_BINS 64
+
+/* Equidistant bins [a0 + i width, a0 + (i+1) width], 0 <= i < n_bins, 1 <= n_bins <=
+   LD_MAX_BINS, width > 0. P_i is the box indicator of Eq. (34) (qoi.r = 0) or its
+   smoothing by Eq. (37) (qoi.r in 1..8, width qoi.delta > 0), taken from the problem's
+   qoi (its kind, a and b are ignored). The paper's p.d.f. uses 20 bins over [0, H]
+   with r = 4 and delta = H/10. */
+typedef struct {
+    double a0, width;
+    int32_t n_bins;
+    int32_t reserved;
+} ld_bins;
+
+/* Bytes of device workspace mlmc_pdf_level_sums needs for n_samples samples. */
+size_t mlmc_pdf_level_sums_workspace(uint64_t n_samples, int32_t n_bins);
+
+/* Per-bin sums of Y_i = P_i(X_l) - P_i(X_{l-1}) (Eq. 16 per component; P_i(X_{-1}) = 0),
+   Y_i^2, P_i(X_l) and P_i(X_l)^2 over samples [sample_begin, sample_begin + n_samples)
+   of `level`: d_out receives n_bins ld_level_sums (device memory, overwritten). The
+   sample paths are those of mlmc_level_sums; a sample whose path ran away is counted
+   as non-finite in every bin. Asynchronous on hip_stream. */
+int mlmc_pdf_level_sums(const ld_problem* problem, ld_integrator integrator,
+                        ld_precision precision, int32_t level, uint64_t sample_begin,
+                        uint64_t n_samples, const ld_bins* bins, ld_level_sums* d_out,
+                        void* d_workspace, size_t workspace_bytes, void* hip_stream);
+
+/* One decision of the adaptive algorithm for the vector QoI (host only). The sample
+   rule is mlmc_plan's with max_i Var[Y_{l,i}] in place of Var[Y_l] (Sec. 6.4); the bias
+   test takes the largest per-bin bias estimate; eps is an absolute RMSE per bin. */
+typedef struct {
+    int32_t L, n_bins;
+    uint64_t n[LD_MAX_LEVELS];                      /* finite samples per level */
+    double sum1[LD_MAX_LEVELS][LD_MAX_BINS];        /* sum of Y_{l,i} */
+    double sum2[LD_MAX_LEVELS][LD_MAX_BINS];        /* sum of Y_{l,i}^2 */
+    int32_t M0, L_max;
+    double eps;
+    int32_t fixed_L, reserved;
+    uint64_t N_init;
+    double alpha;                                   /* <= 0: fit on max_i |Yhat_{l,i}| */
+} ld_pdf_plan_in;
+
+typedef struct {
+    int32_t status, L;                              /* as ld_plan_out */
+    uint64_t dn[LD_MAX_LEVELS];
+    double V[LD_MAX_LEVELS];                        /* max_i Var[Y_{l,i}] */
+    double estimate[LD_MAX_BINS];                   /* sum_l Yhat_{l,i} */
+    double bias_est, stat_var, alpha;               /* maxima over the bins */
+} ld_pdf_plan_out;
+
+int mlmc_plan_pdf(const ld_pdf_plan_in* in, ld_pdf_plan_out* out);
+
+typedef enum { LD_MLMC = 0, LD_STMC = 1 } ld_estimator;
+
+typedef struct {
+    double estimate[LD_MAX_BINS];   /* E[P_i(X_T)] per bin */
+    double bias_est, stat_var, rmse_est;
+    int32_t L, iterations, status, estimator;
+    uint64_t N[LD_MAX_LEVELS];      /* samples per level (StMC: N[0] on level L) */
+    uint64_t n_nonfinite;
+    double V[LD_MAX_LEVELS];        /* max_i Var[Y_{l,i}] (StMC: max_i Var[P_i]) */
+    double fine_steps;              /* coupled (StMC: single) particle-steps drawn */
+    double wall_seconds;
+    double device_seconds;          /* path and bins kernels (HIP events) */
+} ld_pdf_result;
+
+/* Binned-concentration estimate to absolute RMSE eps per bin. LD_MLMC: the adaptive
+   driver of mlmc_estimate with mlmc_plan_pdf's decisions (opts.eps_is_relative must
+   be 0). LD_STMC: standard Monte Carlo (Sec. 3.2) on the single fine path of step
+   T / (M0 2^L), L = opts.fixed_L (>= 0): opts.N_init samples, then
+   N = ceil(2 max_i Var[P_i] / eps^2), topped up while that exceeds the samples drawn
+   by more than 1 %. Blocks until done; opts.d_workspace is not used (the call
+   allocates and frees its own). */
+int mlmc_estimate_pdf(double eps, const ld_bins* bins, const ld_qoi* qoi,
+                      ld_integrator integrator, const ld_profile* profile,
+                      const ld_estimate_opts* opts, ld_estimator estimator,
+                      ld_pdf_result* out);
+
 /* ---- many estimators at once: the engine ---------------------------------------- */
 
 /* The engine runs many independent MLMC estimates (queries) together. Each iteration

@@ -30,6 +30,8 @@ EXPORTED = ["mlmc_level_sums_workspace", "mlmc_level_sums", "mlmc_level_sums_bat
             "mlmc_estimate_default_opts", "mlmc_estimate_workspace", "mlmc_estimate",
             "ld_engine_default_opts", "ld_engine_create", "ld_engine_destroy", "ld_engine_submit",
             "ld_engine_step", "ld_engine_result", "ld_engine_release", "ld_engine_stats",
+            "mlmc_pdf_level_sums_workspace", "mlmc_pdf_level_sums", "mlmc_plan_pdf",
+            "mlmc_estimate_pdf",
             "mlmc_estimate_batch", "ld_engine_autotune",
             "ld_server_default_opts", "ld_server_create", "ld_server_destroy", "ld_server_submit",
             "ld_server_wait", "ld_server_stats_get", "ld_server_clock",
@@ -128,6 +130,39 @@ class Query(C.Structure):
                 ("alpha", C.c_double), ("max_fine_steps", C.c_double)]
 
 
+MAX_BINS = 64
+ESTIMATORS = {"mlmc": 0, "stmc": 1}
+
+
+class Bins(C.Structure):
+    _fields_ = [("a0", C.c_double), ("width", C.c_double), ("n_bins", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class PdfPlanIn(C.Structure):
+    _fields_ = [("L", C.c_int32), ("n_bins", C.c_int32), ("n", C.c_uint64 * MAX_LEVELS),
+                ("sum1", (C.c_double * MAX_BINS) * MAX_LEVELS),
+                ("sum2", (C.c_double * MAX_BINS) * MAX_LEVELS),
+                ("M0", C.c_int32), ("L_max", C.c_int32), ("eps", C.c_double),
+                ("fixed_L", C.c_int32), ("reserved", C.c_int32), ("N_init", C.c_uint64),
+                ("alpha", C.c_double)]
+
+
+class PdfPlanOut(C.Structure):
+    _fields_ = [("status", C.c_int32), ("L", C.c_int32), ("dn", C.c_uint64 * MAX_LEVELS),
+                ("V", C.c_double * MAX_LEVELS), ("estimate", C.c_double * MAX_BINS),
+                ("bias_est", C.c_double), ("stat_var", C.c_double), ("alpha", C.c_double)]
+
+
+class PdfResult(C.Structure):
+    _fields_ = [("estimate", C.c_double * MAX_BINS), ("bias_est", C.c_double),
+                ("stat_var", C.c_double), ("rmse_est", C.c_double), ("L", C.c_int32),
+                ("iterations", C.c_int32), ("status", C.c_int32), ("estimator", C.c_int32),
+                ("N", C.c_uint64 * MAX_LEVELS), ("n_nonfinite", C.c_uint64),
+                ("V", C.c_double * MAX_LEVELS), ("fine_steps", C.c_double),
+                ("wall_seconds", C.c_double), ("device_seconds", C.c_double)]
+
+
 class ServerOpts(C.Structure):
     _fields_ = [("engine", EngineOpts), ("policy", C.c_int32), ("max_queued", C.c_int32)]
 
@@ -188,6 +223,13 @@ def load():
     lib.mlmc_estimate_batch.argtypes = [P(Query), C.c_int32, P(EngineOpts), P(EstimateResult)]
     lib.ld_engine_autotune.argtypes = [P(Query), C.c_int32, P(EngineOpts), C.c_int32,
                                        P(EngineOpts), P(C.c_double)]
+    lib.mlmc_pdf_level_sums_workspace.argtypes = [C.c_uint64, C.c_int32]
+    lib.mlmc_pdf_level_sums_workspace.restype = C.c_size_t
+    lib.mlmc_pdf_level_sums.argtypes = [P(Problem), C.c_int, C.c_int, C.c_int32, C.c_uint64,
+                                        C.c_uint64, P(Bins), V, V, C.c_size_t, V]
+    lib.mlmc_plan_pdf.argtypes = [P(PdfPlanIn), P(PdfPlanOut)]
+    lib.mlmc_estimate_pdf.argtypes = [C.c_double, P(Bins), P(Qoi), C.c_int, P(Profile),
+                                      P(EstimateOpts), C.c_int, P(PdfResult)]
     lib.ld_server_default_opts.argtypes = [P(ServerOpts)]
     lib.ld_server_default_opts.restype = None
     lib.ld_server_create.argtypes = [P(ServerOpts), P(C.c_void_p)]
@@ -523,6 +565,67 @@ def opts_dict(o: EngineOpts) -> dict:
             "hbm_budget_bytes": o.hbm_budget_bytes, "blocks_per_cu": o.blocks_per_cu,
             "target_tiles": o.target_tiles, "pipe_max_samples": o.pipe_max_samples,
             "pipe_min_steps": o.pipe_min_steps, "use_graph": bool(o.use_graph)}
+
+
+def make_bins(a0: float, width: float, n_bins: int) -> Bins:
+    return Bins(a0=float(a0), width=float(width), n_bins=int(n_bins), reserved=0)
+
+
+def pdf_level_sums(cfg, level, begin, n, a0, width, n_bins, precision="fp64", stream=None) -> list:
+    """mlmc_pdf_level_sums: per-bin sums of the binned concentration (Sec. 6.4)."""
+    torch = _torch()
+    lib = load()
+    ws = torch.empty(max(1, lib.mlmc_pdf_level_sums_workspace(n, n_bins)), dtype=torch.uint8, device="cuda")
+    out = torch.zeros(n_bins * C.sizeof(LevelSums), dtype=torch.uint8, device="cuda")
+    b = make_bins(a0, width, n_bins)
+    _check(lib.mlmc_pdf_level_sums(C.byref(make_problem(cfg)), INTEGRATORS[cfg["integrator"]],
+                                   PRECISIONS[precision], level, begin, n, C.byref(b),
+                                   C.c_void_p(out.data_ptr()), C.c_void_p(ws.data_ptr()),
+                                   ws.numel(), _stream_handle(stream)))
+    torch.cuda.synchronize()
+    raw = out.cpu().numpy().tobytes()
+    sz = C.sizeof(LevelSums)
+    return [sums_to_dict(LevelSums.from_buffer_copy(raw[i * sz:(i + 1) * sz])) for i in range(n_bins)]
+
+
+def pdf_plan(d: dict) -> dict:
+    """mlmc_plan_pdf (host only)."""
+    pin = PdfPlanIn()
+    pin.L, pin.n_bins = d["L"], d["n_bins"]
+    for l in range(d["L"] + 1):
+        pin.n[l] = int(d["n"][l])
+        for i in range(d["n_bins"]):
+            pin.sum1[l][i] = d["sum1"][l][i]
+            pin.sum2[l][i] = d["sum2"][l][i]
+    pin.M0, pin.eps, pin.L_max = d["M0"], d["eps"], d.get("L_max", 20)
+    pin.fixed_L, pin.N_init, pin.alpha = d.get("fixed_L", -1), d.get("N_init", 10000), d.get("alpha", 1.0)
+    out = PdfPlanOut()
+    _check(load().mlmc_plan_pdf(C.byref(pin), C.byref(out)))
+    L = out.L
+    return {"status": out.status, "L": L, "dn": [int(out.dn[l]) for l in range(L + 1)],
+            "V": list(out.V[: d["L"] + 1]), "estimate": list(out.estimate[: d["n_bins"]]),
+            "bias_est": out.bias_est, "stat_var": out.stat_var, "alpha": out.alpha}
+
+
+def estimate_pdf(eps, cfg, a0, width, n_bins, *, estimator="mlmc", stream=None, **kw) -> dict:
+    """mlmc_estimate_pdf: binned concentration to absolute RMSE eps per bin."""
+    _torch()
+    lib = load()
+    kw.setdefault("eps_is_relative", False)
+    o = estimate_opts(cfg, stream=stream, **kw)
+    r = PdfResult()
+    b = make_bins(a0, width, n_bins)
+    q, prof = make_qoi(cfg), make_profile(cfg)
+    rc = lib.mlmc_estimate_pdf(float(eps), C.byref(b), C.byref(q), INTEGRATORS[cfg["integrator"]],
+                               C.byref(prof), C.byref(o), ESTIMATORS[estimator], C.byref(r))
+    _check(rc, ok=(LD_OK, LD_WARN_NOT_CONVERGED, LD_ENONFINITE))
+    L = r.L
+    nl = 1 if estimator == "stmc" else L + 1
+    return {"rc": rc, "estimate": list(r.estimate[:n_bins]), "bias_est": r.bias_est,
+            "stat_var": r.stat_var, "rmse_est": r.rmse_est, "L": L, "iterations": r.iterations,
+            "status": r.status, "N": [int(r.N[l]) for l in range(nl)],
+            "n_nonfinite": int(r.n_nonfinite), "V": list(r.V[:nl]), "fine_steps": r.fine_steps,
+            "wall_seconds": r.wall_seconds, "device_seconds": r.device_seconds}
 
 
 class Server:

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libldmlmc.so")
-SOURCES = ["kernels.hip", "api.cpp", "driver.cpp", "engine.cpp", "server.cpp", "smoothing.cpp"]
+SOURCES = ["kernels.hip", "api.cpp", "driver.cpp", "engine.cpp", "server.cpp", "pdf.cpp", "smoothing.cpp"]
 
 # -packed-fp32-ops: never emit v_pk_{add,mul,fma}_f32 (packed FP32 has given silent
 # wrong results on these boxes). No fast-math: the compensated sums and the expm1-based

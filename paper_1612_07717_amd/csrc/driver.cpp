@@ -93,6 +93,34 @@ void merge_into(HostSums& acc, const ld_level_sums& add) {
 
 }  // namespace
 
+// The decision of one iteration (shared by the scalar and the vector planners), given
+// each level's variance V[0..in->L], the bias estimate and the absolute tolerance:
+// levels needing more than 1 % extra samples get them (status 0); otherwise the
+// estimate has converged (1), or the bias test adds level L + 1 with V_{L+1} = V_L / 4
+// (condition (iii)) and at least N_init samples (0), or L_max is reached (2).
+int ldm::decide(const ld_plan_in* in, const double* Vl, double bias, double eps_abs, uint64_t* dn,
+                int32_t* L_out) {
+    const int32_t L = in->L;
+    *L_out = L;
+    variance_rule(in, L, Vl, eps_abs, dn);
+    bool more = false;
+    for (int32_t l = 0; l <= L; ++l)
+        if ((double)dn[l] > 0.01 * (double)in->n[l]) more = true;
+    if (more) return 0;
+    for (int32_t l = 0; l <= L; ++l) dn[l] = 0;
+    if (in->fixed_L >= 0 || L < 1 || bias <= eps_abs / std::sqrt(2.0)) return 1;
+    if (L >= in->L_max || L + 1 >= LD_MAX_LEVELS) return 2;
+    double V[LD_MAX_LEVELS];
+    for (int32_t l = 0; l <= L; ++l) V[l] = Vl[l];
+    V[L + 1] = V[L] / 4.0;
+    variance_rule(in, L + 1, V, eps_abs, dn);
+    dn[L + 1] = std::max(dn[L + 1], in->N_init);
+    *L_out = L + 1;
+    return 0;
+}
+
+double ldm::fit_alpha(const double* Yhat, int32_t L) { return fitted_alpha(Yhat, L); }
+
 extern "C" {
 
 int mlmc_plan(const ld_plan_in* in, ld_plan_out* out) {
@@ -129,30 +157,9 @@ int mlmc_plan(const ld_plan_in* in, ld_plan_out* out) {
         out->status = 2;
         return LD_OK;
     }
-    variance_rule(in, L, out->V, out->eps_abs, out->dn);
-    bool more = false;
-    for (int32_t l = 0; l <= L; ++l)
-        if ((double)out->dn[l] > 0.01 * (double)in->n[l]) more = true;
-    if (more) {
-        out->status = 0;
-        return LD_OK;
-    }
-    for (int32_t l = 0; l <= L; ++l) out->dn[l] = 0;
-    if (in->fixed_L >= 0 || L < 1 || out->bias_est <= out->eps_abs / std::sqrt(2.0)) {
-        out->status = 1;
-        return LD_OK;
-    }
-    if (L >= in->L_max || L + 1 >= LD_MAX_LEVELS) {
-        out->status = 2;
-        return LD_OK;
-    }
-    double V[LD_MAX_LEVELS];
-    for (int32_t l = 0; l <= L; ++l) V[l] = out->V[l];
-    V[L + 1] = V[L] / 4.0;   // variance decay h^2 (condition (iii))
-    variance_rule(in, L + 1, V, out->eps_abs, out->dn);
-    out->dn[L + 1] = std::max(out->dn[L + 1], in->N_init);
-    out->L = L + 1;
-    out->status = 0;
+    int32_t Lout = L;
+    out->status = decide(in, out->V, out->bias_est, out->eps_abs, out->dn, &Lout);
+    out->L = Lout;
     return LD_OK;
 }
 

@@ -16,6 +16,13 @@ int validate_problem(const ld_problem* p);
 // coupled fine steps sum_l N_l M0 2^l above max_fine_steps (> 0); false without a budget.
 bool exceeds_budget(double max_fine_steps, int32_t M0, const uint64_t* drawn, const uint64_t* dn,
                     int32_t L);
+// The decision step shared by mlmc_plan and mlmc_plan_pdf (driver.cpp): fills dn and
+// *L_out from each level's variance Vl[0..in->L] (uses in->n, L, M0, L_max, fixed_L,
+// N_init), returns the status (0 more samples, 1 converged, 2 stopped at L_max).
+int decide(const ld_plan_in* in, const double* Vl, double bias, double eps_abs, uint64_t* dn,
+           int32_t* L_out);
+// Least-squares weak order from |Yhat_l|, l = 1..L, clamped to [0.5, 2] (1 if unfit).
+double fit_alpha(const double* Yhat, int32_t L);
 // Validates an engine query as mlmc_estimate validates its arguments (engine.cpp).
 int validate_query(const ld_query* q);
 // Symplectic Euler is stable only for lambda h < 2 (Sec. 3.1); returns LD_EUNSTABLE if

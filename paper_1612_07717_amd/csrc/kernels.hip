@@ -485,6 +485,94 @@ __global__ __launch_bounds__(kBlock) void merge_kernel(const KArgs args,
     if (threadIdx.x == 0) store_sums(&out[item.out_slot], acc);
 }
 
+// ---------------------------------------------------------------------------------
+// Binned concentration (vector QoI of Sec. 6.4). The path kernels dump the terminal
+// positions (X_f, X_c) of a range (NaN for a path that ran away); pdf_bins_kernel then
+// forms, per bin, compensated sums of Y_i = P_i(X_f) - P_i(X_c), Y_i^2, P_i(X_f) and
+// its square, with P_i the box of Eq. (34) or its smoothing by Eq. (37). A wave holds
+// floor(64 / n_bins) samples side by side, one lane per (sample, bin); each block takes
+// kPdfChunk consecutive samples and reduces its sample streams per bin in a fixed
+// order, and pdf_merge_kernel folds the blocks of each bin in a fixed tree.
+// ---------------------------------------------------------------------------------
+__device__ __forceinline__ double box_qoi(const KProblem& kp, double x, double a, double b) {
+    if (kp.r == 0) return (x <= b ? 1.0 : 0.0) - (x <= a ? 1.0 : 0.0);
+    return g_r(kp, (x - b) * kp.inv_delta) - g_r(kp, (x - a) * kp.inv_delta);
+}
+
+__global__ __launch_bounds__(kBlock) void pdf_bins_kernel(const KBins bins, const KProblem kp,
+                                                          const double* __restrict__ dump,
+                                                          ld_level_sums* __restrict__ partials) {
+    const int k = bins.n_bins;
+    const int spw = 64 / k;                              // sample streams per wave
+    const int lane = threadIdx.x & 63, wave = (int)wave_index();
+    const int sub = lane / k, bin = lane - sub * k;
+    const bool on = sub < spw;
+    const int streams = (kBlock / 64) * spw;
+    const int stream = wave * spw + sub;
+    const uint64_t lo = (uint64_t)blockIdx.x * kPdfChunk;
+    const uint64_t hi = lo + kPdfChunk < bins.n ? lo + kPdfChunk : bins.n;
+    const double a = bins.a0 + (double)bin * bins.width;
+    const double b = bins.a0 + (double)(bin + 1) * bins.width;
+    Acc acc;
+    acc_zero(acc);
+    if (on) {
+        for (uint64_t j = lo + (uint64_t)stream; j < hi; j += (uint64_t)streams) {
+            const double xf = dump[2 * j], xc = dump[2 * j + 1];
+            const bool bad = !isfinite(xf) || (bins.level != 0 && !isfinite(xc));
+            const double pf = box_qoi(kp, xf, a, b);
+            const double pc = (bins.level == 0) ? 0.0 : box_qoi(kp, xc, a, b);
+            accumulate(acc, pf, pc, bad);
+        }
+    }
+    __shared__ Acc sh[kBlock];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < (unsigned)k) {
+        Acc t;
+        acc_zero(t);
+        for (int st = 0; st < streams; ++st) {               // fixed order of the streams
+            const Acc& o = sh[(st / spw) * 64 + (st % spw) * k + (int)threadIdx.x];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) neumaier_merge(t.s[q], t.c[q], o.s[q], o.c[q]);
+            t.n += o.n;
+            t.nbad += o.nbad;
+        }
+        store_sums(&partials[(uint64_t)blockIdx.x * k + threadIdx.x], t);
+    }
+}
+
+// One block per bin: the block partials of that bin, strided over the threads and
+// reduced in the fixed tree of block_reduce.
+__global__ __launch_bounds__(kBlock) void pdf_merge_kernel(const ld_level_sums* __restrict__ partials,
+                                                           uint32_t n_blocks, int32_t n_bins,
+                                                           ld_level_sums* __restrict__ out) {
+    const int bin = blockIdx.x;
+    Acc acc;
+    acc_zero(acc);
+    for (uint32_t j = threadIdx.x; j < n_blocks; j += kBlock) {
+        const ld_level_sums p = partials[(uint64_t)j * n_bins + bin];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) neumaier_merge(acc.s[q], acc.c[q], p.s[q], p.c[q]);
+        acc.n += p.n;
+        acc.nbad += p.n_nonfinite;
+    }
+    block_reduce(acc);
+    if (threadIdx.x == 0) store_sums(&out[bin], acc);
+}
+
+int launch_pdf_bins(const KBins& bins, const KProblem& kp, const double* d_dump,
+                    ld_level_sums* d_partials, ld_level_sums* d_out, void* stream) {
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t nb = pdf_blocks(bins.n);
+    if (nb > 0) {
+        hipLaunchKernelGGL(pdf_bins_kernel, dim3(nb), dim3(kBlock), 0, s, bins, kp, d_dump, d_partials);
+        if (hipGetLastError() != hipSuccess) return LD_EDEVICE;
+    }
+    hipLaunchKernelGGL(pdf_merge_kernel, dim3(bins.n_bins), dim3(kBlock), 0, s, d_partials, nb, bins.n_bins,
+                       d_out);
+    return hipGetLastError() == hipSuccess ? LD_OK : LD_EDEVICE;
+}
+
 using LevelKernel = void (*)(const KArgs, ld_level_sums*, double*);
 
 template <typename R>

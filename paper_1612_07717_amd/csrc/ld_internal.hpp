@@ -112,6 +112,22 @@ int launch_engine_iteration(int precision, uint32_t grid_blocks, uint32_t profil
                             ld_level_sums* d_partials, uint32_t* d_counters,
                             const KRange* d_ranges, ld_level_sums* d_running,
                             ld_level_sums* d_range_out, void* stream);
+// Binned concentration: bins [a0 + i width, a0 + (i+1) width], i < n_bins (<= 64),
+// over a dump of n (X_f, X_c) pairs of `level`.
+struct KBins {
+    double a0, width;
+    int32_t n_bins, level;
+    uint64_t n;
+};
+constexpr uint32_t kPdfChunk = 2048;                // dumped samples per bins block
+constexpr int kMaxBins = 64;
+inline uint32_t pdf_blocks(uint64_t n) { return (uint32_t)((n + kPdfChunk - 1) / kPdfChunk); }
+// pdf_bins_kernel over the dump, then the per-bin merge into d_out[0 .. n_bins).
+// d_partials holds pdf_blocks(n) * n_bins sums. kp: the problem with the box QoI (r,
+// delta, smoothing coefficients).
+int launch_pdf_bins(const KBins& bins, const KProblem& kp, const double* d_dump,
+                    ld_level_sums* d_partials, ld_level_sums* d_out, void* stream);
+
 int launch_clear_sums(ld_level_sums* d_sums, uint32_t n, void* stream);
 
 }  // namespace ldm

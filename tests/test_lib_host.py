@@ -56,7 +56,9 @@ def test_struct_layouts_match_header(tmp_path):
                "ld_plan_out": ld.PlanOut, "ld_estimate_opts": ld.EstimateOpts,
                "ld_estimate_result": ld.EstimateResult, "ld_engine_opts": ld.EngineOpts,
                "ld_query": ld.Query, "ld_server_opts": ld.ServerOpts,
-               "ld_request_times": ld.RequestTimes, "ld_server_stats": ld.ServerStats}
+               "ld_request_times": ld.RequestTimes, "ld_server_stats": ld.ServerStats,
+               "ld_bins": ld.Bins, "ld_pdf_plan_in": ld.PdfPlanIn, "ld_pdf_plan_out": ld.PdfPlanOut,
+               "ld_pdf_result": ld.PdfResult}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ldmlmc.h"', "int main(void){"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -202,3 +204,61 @@ def test_negative_cost_budget_is_rejected(lib):
     with pytest.raises(ld.LdError) as e:
         ld.estimate(1e-2, W.neutral(300.0, "GL"), max_fine_steps=-1.0)
     assert e.value.status == ld.LD_EINVAL
+
+
+def _random_pdf_inputs(rng, n_cases):
+    for _ in range(n_cases):
+        L = int(rng.integers(0, 7))
+        k = int(rng.integers(1, 25))
+        n = [int(rng.integers(2, 200000)) for _ in range(L + 1)]
+        s1 = [[0.0] * k for _ in range(L + 1)]
+        s2 = [[0.0] * k for _ in range(L + 1)]
+        for l in range(L + 1):
+            for i in range(k):
+                mean = float(rng.normal(0, 0.05)) * 2.0 ** -l
+                var = float(10.0 ** rng.uniform(-6, -1)) * 4.0 ** -l
+                s1[l][i] = mean * n[l]
+                s2[l][i] = var * (n[l] - 1) + n[l] * mean * mean
+        yield dict(L=L, n_bins=k, n=n, sum1=s1, sum2=s2, M0=int(rng.choice([8, 40, 80])),
+                   eps=float(10.0 ** rng.uniform(-4, -1)), L_max=int(rng.integers(L, 12)),
+                   fixed_L=int(rng.choice([-1, -1, L])), N_init=int(rng.choice([1000, 10000])),
+                   alpha=float(rng.choice([1.0, 2.0, 0.0])))
+
+
+def test_pdf_planner_matches_oracle_planner(lib, orc):
+    rng = np.random.default_rng(12)
+    for d in _random_pdf_inputs(rng, 600):
+        a, b = ld.pdf_plan(d), orc.pdf_plan(d)
+        assert (a["status"], a["L"], a["dn"]) == (b["status"], b["L"], b["dn"]), d["L"]
+        for key in ("bias_est", "stat_var", "alpha"):
+            assert a[key] == pytest.approx(b[key], rel=1e-12, abs=1e-300), key
+        assert np.allclose(a["estimate"], b["estimate"], rtol=1e-12, atol=1e-300)
+        assert np.allclose(a["V"], b["V"], rtol=1e-12, atol=0)
+
+
+def test_pdf_arguments_rejected_without_device(lib):
+    cfg = W.neutral(300.0, "GL", r=4, delta=100.0)
+    p = ld.make_problem(cfg)
+    fake = C.c_void_p(0x1000)   # never dereferenced: validation fails first
+    for bins in (ld.make_bins(0.0, 50.0, 0), ld.make_bins(0.0, 50.0, 65), ld.make_bins(0.0, 0.0, 20),
+                 ld.make_bins(float("nan"), 50.0, 20)):
+        assert lib.mlmc_pdf_level_sums(C.byref(p), 1, 0, 0, 0, 100, C.byref(bins), fake, fake,
+                                       1 << 30, None) == ld.LD_EINVAL
+    bad_r = ld.make_problem(dict(cfg, r=9))
+    assert lib.mlmc_pdf_level_sums(C.byref(bad_r), 1, 0, 0, 0, 100, C.byref(ld.make_bins(0.0, 50.0, 20)),
+                                   fake, fake, 1 << 30, None) == ld.LD_EINVAL
+    good = ld.make_bins(0.0, 50.0, 20)
+    assert lib.mlmc_pdf_level_sums(C.byref(p), 1, 0, 0, 0, 100, C.byref(good), fake, fake, 0,
+                                   None) == ld.LD_ENOMEM
+    assert lib.mlmc_pdf_level_sums_workspace(1000, 0) == 0
+    assert lib.mlmc_pdf_level_sums_workspace(1000, 20) >= 16 * 1000
+    res = ld.PdfResult()
+    q, prof = ld.make_qoi(cfg), ld.make_profile(cfg)
+    o = ld.estimate_opts(cfg)
+    assert lib.mlmc_estimate_pdf(1e-3, C.byref(good), C.byref(q), 1, C.byref(prof), C.byref(o),
+                                 1, C.byref(res)) == ld.LD_EINVAL       # StMC needs fixed_L
+    o_rel = ld.estimate_opts(cfg, eps_is_relative=True)
+    assert lib.mlmc_estimate_pdf(1e-3, C.byref(good), C.byref(q), 1, C.byref(prof), C.byref(o_rel),
+                                 0, C.byref(res)) == ld.LD_EINVAL       # absolute eps only
+    assert lib.mlmc_estimate_pdf(1e-3, C.byref(good), C.byref(q), 1, C.byref(prof), C.byref(o),
+                                 5, C.byref(res)) == ld.LD_EINVAL       # unknown estimator
