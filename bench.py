@@ -68,6 +68,20 @@ def hbm_traffic(precision: str):
     return d.get("bytes_per_launch")
 
 
+def valu_issue(precision: str):
+    """Measured VALU issue utilisation of the dominant kernel's launches (committed
+    rocprofv3 counter summary), or None when missing or taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"level_kernel_{precision}_single_large_valu.json")
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except OSError:
+        return None
+    if d.get("kernel_hash") != kernel_hash():
+        return None
+    return {f"{r['blocks']}_blocks": round(r["issue_frac"], 3) for r in d["launches"] if r.get("issue_frac")}
+
+
 def cpu_baseline(cfg, N_levels, target_steps=2.5e8):
     """The oracle on a bounded sample: each level's samples scaled down by the same
     factor so the sample has about target_steps coupled fine steps."""
@@ -183,6 +197,55 @@ def serving_report(ld, rate, duration, seed, n_init, fifo_seconds=None, precisio
 
 BATCHED_N_INIT = 1000
 
+# The paper's measured runtimes (seconds, one core of an i5-4460, its own C++ code) for
+# the 20-bin concentration p.d.f. at eps = 4e-3 (Table of Sec. 6.4, release heights).
+PAPER_PDF_SECONDS = {
+    50.0: {"StMC-SE": 2561.41, "StMC-GL": 321.77, "StMC-BAOAB": 91.21, "MLMC-SE": 218.52, "MLMC-GL": 265.84},
+    100.0: {"StMC-SE": 867.32, "StMC-GL": 277.72, "StMC-BAOAB": 79.25, "MLMC-SE": 120.17, "MLMC-GL": 125.92},
+    200.0: {"StMC-SE": 316.33, "StMC-GL": 280.04, "StMC-BAOAB": 78.15, "MLMC-SE": 64.78, "MLMC-GL": 103.69},
+}
+PDF_BINS = (0.0, 50.0, 20)                       # 20 bins of 0.05 H over [0, H]
+PDF_EPS = 4e-3 * PDF_BINS[1] / 1000.0            # RMSE 4e-3 of the density (units 1/H) per bin
+
+
+def pdf_config(z0, integ):
+    """The paper's p.d.f. set-up: release at z0 with U_0 = 0.1 m/s, T = 1000 s, M_0 = 80
+    (SE, GL) or 40 (BAOAB), smoothed boxes r = 4, delta = 0.1 H."""
+    return W.problem(integrator=integ, z0=float(z0), w0=0.1, release="fixed",
+                     M0=40 if integ == "BAOAB" else 80, r=4, delta=100.0)
+
+
+def pdf_report(ld, precisions=("fp64", "fp32")):
+    """MLMC for each integrator and release height, then standard Monte Carlo on the
+    finest step MLMC needed (the step the bias test asks for); wall time of each call."""
+    import torch
+    a0, w, k = PDF_BINS
+    rows = []
+    for prec in precisions:
+        for integ in ("SE", "GL", "BAOAB"):           # warm-up: module load, first allocations
+            ld.estimate_pdf(1e-2, pdf_config(100.0, integ), a0, w, k, precision=prec, N_init=1000, L_max=3)
+        torch.cuda.synchronize()
+        for z0 in (50.0, 100.0, 200.0):
+            for integ in ("SE", "GL", "BAOAB"):
+                cfg = pdf_config(z0, integ)
+                t0 = time.perf_counter()
+                m = ld.estimate_pdf(PDF_EPS, cfg, a0, w, k, precision=prec, L_min=2, L_max=12, N_init=10000)
+                t_m = time.perf_counter() - t0
+                t0 = time.perf_counter()
+                st = ld.estimate_pdf(PDF_EPS, cfg, a0, w, k, estimator="stmc", fixed_L=m["L"],
+                                     precision=prec, N_init=10000)
+                t_s = time.perf_counter() - t0
+                for name, r, t in ((f"MLMC-{integ}", m, t_m), (f"StMC-{integ}", st, t_s)):
+                    paper = PAPER_PDF_SECONDS[z0].get(name)
+                    rows.append({"release_m": z0, "method": name, "precision": prec, "seconds": t,
+                                 "paper_seconds": paper, "speedup_vs_paper": (paper / t) if paper else None,
+                                 "L": r["L"], "N": r["N"], "fine_steps": r["fine_steps"],
+                                 "rmse_est": r["rmse_est"], "status": r["status"],
+                                 "density": [p / (w / 1000.0) for p in r["estimate"]]})
+                print(json.dumps({"progress": "pdf", **{k2: v for k2, v in rows[-2].items() if k2 != "density"}}),
+                      file=sys.stderr, flush=True)
+    return rows
+
 
 def batched_report(ld, steps, warmup):
     """64 independent estimators (mixed release height, tolerance, integrator and QoI)
@@ -228,7 +291,7 @@ def batched_report(ld, steps, warmup):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="single_large", choices=["single_large", "batched", "serving"])
+    ap.add_argument("--workload", default="single_large", choices=["single_large", "batched", "serving", "pdf"])
     ap.add_argument("--rate", type=float, default=100.0, help="serving: arrivals per second")
     ap.add_argument("--duration", type=float, default=60.0, help="serving: seconds of arrivals")
     ap.add_argument("--fifo-seconds", type=float, default=None,
@@ -276,6 +339,22 @@ def main():
                                                  "U[50,950] m, relative eps log-uniform "
                                                  "[3e-4,1e-2], integrator and QoI mixed"},
                           "serving": rep}), flush=True)
+        return
+    if args.workload == "pdf":
+        rows = pdf_report(ld)
+        fp64 = [r for r in rows if r["precision"] == "fp64" and r["paper_seconds"]]
+        gpu_s = sum(r["seconds"] for r in fp64)
+        paper_s = sum(r["paper_seconds"] for r in fp64)
+        print(json.dumps({"metric": "time-to-eps of the 20-bin concentration p.d.f. (15 paper runs)",
+                          "value": gpu_s, "unit": "s (sum, FP64 paths)", "n_gpus": 1,
+                          "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+                          "vs_baseline": gpu_s / paper_s,
+                          "config": {"workload": "binned concentration, 20 bins of 50 m, r = 4, "
+                                                 "delta = 100 m, density RMSE 4e-3, release 50/100/200 m, "
+                                                 "U_0 = 0.1 m/s, T = 1000 s, M_0 = 80 (SE, GL) / 40 (BAOAB)",
+                                     "paper_seconds_sum": paper_s,
+                                     "paper_hardware": "one core of an Intel i5-4460, the paper's C++ code"},
+                          "runs": rows}), flush=True)
         return
     if args.workload == "batched":
         rep = batched_report(ld, args.steps, args.warmup)
@@ -353,7 +432,8 @@ def main():
                      "frac": achieved / peak, "traffic": hbm_traffic(args.precision),
                      "kernel": f"level_kernel<{'float' if args.precision == 'fp32' else 'double'}>",
                      "ops_per_coupled_step": ops,
-                     "avg_launch_ms": 1e3 * dev_s / launches},
+                     "avg_launch_ms": 1e3 * dev_s / launches,
+                     "valu_issue_util": valu_issue(args.precision)},
     }
     if args.serve_seconds > 0:
         rep = serving_report(ld, 100.0, args.serve_seconds, seed=11, n_init=args.n_init)
