@@ -49,7 +49,7 @@ class Problem(C.Structure):
         ("qoi_kind", C.c_int32), ("r", C.c_int32),
         ("qa", C.c_double), ("qb", C.c_double), ("delta", C.c_double),
         ("T", C.c_double), ("M0", C.c_int32), ("stream_id", C.c_uint32),
-        ("seed", C.c_uint64),
+        ("seed", C.c_uint64), ("x_adapt", C.c_double),
     ]
 
 
@@ -177,6 +177,7 @@ def make_problem(cfg: dict) -> Problem:
     p.M0 = int(cfg["M0"])
     p.stream_id = int(cfg["stream_id"])
     p.seed = int(cfg["seed"])
+    p.x_adapt = float(cfg.get("x_adapt", 0.0))
     return p
 
 

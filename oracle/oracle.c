@@ -365,10 +365,95 @@ static void initial_state(const oracle_problem* p, int32_t level, uint64_t sampl
     }
 }
 
+/* ================================================================================== */
+/* Adaptive, non-nested timesteps for symplectic Euler (Sec. 7).                        */
+/* ================================================================================== */
+
+/* Eq. (8) driven by the Brownian increment dW of the step (dW replaces sqrt(h) xi). */
+static int step_se_dw(const oracle_problem* p, double h, double st[3], double dW) {
+    double x = st[0], u = st[1], s = st[2];
+    double lambda, sigma;
+    coefficients(p, x, &lambda, &sigma);
+    double u1 = (1.0 - lambda * h) * u - oracle_dVdX(p, x, u) * h + sigma * dW;
+    double x1 = x + u1 * h;
+    int rc = fold(p->H, &x1, &u1, &s);
+    st[0] = x1; st[1] = u1; st[2] = s;
+    return rc;
+}
+
+/* End (in ticks) of the step a path at x starts at tick t: base step `base` ticks,
+   shortened to floor(lambda(X_adapt) / lambda(x) base) below the reference height. */
+static uint64_t adaptive_end(const oracle_problem* p, double lam_adapt, double x, uint64_t t,
+                             uint64_t base, uint64_t t_end) {
+    double lambda, sigma;
+    coefficients(p, x, &lambda, &sigma);
+    double ratio = lam_adapt / lambda;
+    uint64_t k = base;
+    if (ratio < 1.0) {                          /* also false for a NaN state */
+        k = (uint64_t)floor(ratio * (double)base);
+        if (k < 1) k = 1;
+    }
+    return (t + k < t_end) ? t + k : t_end;
+}
+
+/* One coupled sample with adaptive steps. The merged time grid tau_j is the union of
+   the fine and the coarse time points; interval j gets xi_j (draw j mod 2 of Philox block
+   j / 2, as the uniform scheme's step j). The fine path's increment over its step is the
+   sum of xi_j sqrt(tau_{j+1} - tau_j) over the intervals it covers; the coarse path's is
+   S^(c) times the sum of S_j^(f) xi_j sqrt(tau_{j+1} - tau_j) (Eq. for the adaptive Euler
+   increment), S_j^(f) being the fine path's reflection sign at tau_j. */
+static int run_sample_adaptive(const context* ctx, int32_t level, uint64_t sample,
+                               double fine[3], double coarse[3]) {
+    const oracle_problem* p = &ctx->p;
+    const uint64_t M = (uint64_t)p->M0 << level;
+    const double h = p->T / (double)M;                       /* h_l */
+    const uint64_t tick_base = (uint64_t)1 << ORACLE_TICK_BITS;
+    const double tick = h / (double)tick_base;
+    const uint64_t t_end = M * tick_base;                    /* T in ticks */
+    double lam_adapt, sigma_unused;
+    coefficients(p, p->x_adapt, &lam_adapt, &sigma_unused);
+    double x0, u0;
+    initial_state(p, level, sample, &x0, &u0);
+    fine[0] = x0; fine[1] = u0; fine[2] = 1.0;
+    coarse[0] = x0; coarse[1] = u0; coarse[2] = 1.0;
+    const int naive = (p->coupling == ORACLE_COUPLING_NAIVE);
+    int bad = 0;
+    uint64_t tf = 0, tc = 0, tau = 0, j = 0;
+    uint64_t ef = adaptive_end(p, lam_adapt, fine[0], 0, tick_base, t_end);
+    uint64_t ec = (level == 0) ? t_end : adaptive_end(p, lam_adapt, coarse[0], 0, 2 * tick_base, t_end);
+    double wf = 0.0, wc = 0.0, z[2];
+    while (tf < t_end || (level != 0 && tc < t_end)) {
+        uint64_t next = t_end;
+        if (tf < t_end && ef < next) next = ef;
+        if (level != 0 && tc < t_end && ec < next) next = ec;
+        if (j % 2 == 0) oracle_normals(p, level, sample, (uint32_t)(j / 2), z);
+        double dW = z[j % 2] * sqrt((double)(next - tau) * tick);
+        wf += dW;
+        wc += (naive ? 1.0 : fine[2]) * dW;
+        tau = next;
+        ++j;
+        if (tf < t_end && tau == ef) {
+            bad |= step_se_dw(p, (double)(ef - tf) * tick, fine, wf);
+            tf = ef;
+            wf = 0.0;
+            if (tf < t_end) ef = adaptive_end(p, lam_adapt, fine[0], tf, tick_base, t_end);
+        }
+        if (level != 0 && tc < t_end && tau == ec) {
+            bad |= step_se_dw(p, (double)(ec - tc) * tick, coarse, (naive ? 1.0 : coarse[2]) * wc);
+            tc = ec;
+            wc = 0.0;
+            if (tc < t_end) ec = adaptive_end(p, lam_adapt, coarse[0], tc, 2 * tick_base, t_end);
+        }
+    }
+    return bad;
+}
+
 /* Runs sample `sample` of `level`; fills the terminal fine and coarse states. */
 static int run_sample(const context* ctx, int32_t level, uint64_t sample,
                       double fine[3], double coarse[3]) {
     const oracle_problem* p = &ctx->p;
+    if (p->integrator == ORACLE_SE && p->x_adapt > 0.0)
+        return run_sample_adaptive(ctx, level, sample, fine, coarse);
     uint64_t M = (uint64_t)p->M0 << level;     /* M_l = M_0 2^l */
     double h = p->T / (double)M;               /* h_l = T / M_l */
     double x0, u0;

@@ -56,7 +56,15 @@ typedef struct {
     int32_t M0;             /* timesteps on level 0 */
     uint32_t stream_id;     /* independent random stream, 24 bits */
     uint64_t seed;          /* Philox key */
+    double x_adapt;         /* > 0 (symplectic Euler only): adaptive, non-nested timesteps
+                               below this reference height (Sec. 7); 0: uniform steps */
 } oracle_problem;
+
+/* Adaptive timesteps (Sec. 7): a path at X takes h_n = min(h, lambda(X_adapt) / lambda(X) h)
+   from its base step h (h_l on the fine path, 2 h_l on the coarse path), rounded down to a
+   whole tick of h_l / 2^ORACLE_TICK_BITS (at least one) and cut at T. Time is counted in
+   ticks, so coinciding fine and coarse time points coincide exactly. */
+#define ORACLE_TICK_BITS 20
 
 /* Compensated (Neumaier) sums of Y, Y^2, P_f, P_f^2 over the finite samples. */
 typedef struct {
