@@ -247,6 +247,54 @@ def pdf_report(ld, precisions=("fp64", "fp32")):
     return rows
 
 
+ADAPT_X = 50.0                                   # reference height X_adapt (0.05 H)
+ADAPT_EPS_REL = (1e-2, 5e-3, 2e-3, 1e-3)
+
+
+def adaptive_report(ld, precisions=("fp64", "fp32"), n_bias=1 << 22):
+    """Sec. 7 set-up: the mean-position problem (release 50 m, U_0 = 0.1 m/s, T = 1000 s,
+    M_0 = 40) with symplectic Euler, uniform against adaptive steps (X_adapt = 50 m):
+    E[Y_l] and Var[Y_l] on levels 1..6 from n_bias samples each (the bias of level l is
+    about E[Y_{l+1}] / (2^alpha - 1)), then time-to-eps of the adaptive MLMC driver."""
+    import torch
+    uni = W.problem(integrator="SE", M0=40)
+    ada = dict(uni, x_adapt=ADAPT_X)
+    levels = list(range(1, 7))
+    out = {"levels": [], "runs": []}
+    for name, cfg in (("uniform", uni), ("adaptive", ada)):
+        ld.estimate(1e-2, cfg, precision="fp64", eps_is_relative=True, N_init=1000, L_max=3)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sums = ld.level_sums_batch(cfg, [(l, 0, n_bias) for l in levels], "fp64")
+        dt = time.perf_counter() - t0
+        for l, s in zip(levels, sums):
+            m = s["sum_y"] / s["n"]
+            out["levels"].append({"steps": name, "level": l, "mean_Y": m,
+                                  "var_Y": s["sum_y2"] / s["n"] - m * m, "n": s["n"]})
+        out[f"{name}_level_sums_seconds"] = dt
+    for l in levels:
+        u = next(r for r in out["levels"] if r["steps"] == "uniform" and r["level"] == l)
+        a = next(r for r in out["levels"] if r["steps"] == "adaptive" and r["level"] == l)
+        u["bias_ratio_uniform_over_adaptive"] = abs(u["mean_Y"]) / max(abs(a["mean_Y"]), 1e-300)
+        u["var_ratio_uniform_over_adaptive"] = u["var_Y"] / max(a["var_Y"], 1e-300)
+    for prec in precisions:
+        for eps in ADAPT_EPS_REL:
+            for name, cfg in (("uniform", uni), ("adaptive", ada)):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = ld.estimate(eps, cfg, precision=prec, eps_is_relative=True, N_init=10000,
+                                L_min=2, L_max=12)
+                torch.cuda.synchronize()
+                t = time.perf_counter() - t0
+                out["runs"].append({"precision": prec, "eps_rel": eps, "steps": name, "seconds": t,
+                                    "device_seconds": r["device_seconds"], "L": r["L"], "N": r["N"],
+                                    "nominal_fine_steps": r["fine_steps"], "estimate": r["estimate"],
+                                    "rmse_est": r["rmse_est"], "status": r["status"]})
+                print(json.dumps({"progress": "adaptive", **{k: v for k, v in out["runs"][-1].items()
+                                                             if k != "N"}}), file=sys.stderr, flush=True)
+    return out
+
+
 def batched_report(ld, steps, warmup):
     """64 independent estimators (mixed release height, tolerance, integrator and QoI)
     in one engine: autotuned FP32, the same options in FP64, and the same queries one
@@ -291,7 +339,7 @@ def batched_report(ld, steps, warmup):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="single_large", choices=["single_large", "batched", "serving", "pdf"])
+    ap.add_argument("--workload", default="single_large", choices=["single_large", "batched", "serving", "pdf", "adaptive"])
     ap.add_argument("--rate", type=float, default=100.0, help="serving: arrivals per second")
     ap.add_argument("--duration", type=float, default=60.0, help="serving: seconds of arrivals")
     ap.add_argument("--fifo-seconds", type=float, default=None,
@@ -355,6 +403,20 @@ def main():
                                      "paper_seconds_sum": paper_s,
                                      "paper_hardware": "one core of an Intel i5-4460, the paper's C++ code"},
                           "runs": rows}), flush=True)
+        return
+    if args.workload == "adaptive":
+        rep = adaptive_report(ld)
+        fp64 = [r for r in rep["runs"] if r["precision"] == "fp64"]
+        t_u = sum(r["seconds"] for r in fp64 if r["steps"] == "uniform")
+        t_a = sum(r["seconds"] for r in fp64 if r["steps"] == "adaptive")
+        print(json.dumps({"metric": "time-to-eps, adaptive over uniform symplectic Euler",
+                          "value": t_a / t_u, "unit": "ratio (sum over eps, FP64 paths)", "n_gpus": 1,
+                          "higher_is_better": False, "dtype": "f64", "data": "synthetic",
+                          "vs_baseline": None,
+                          "config": {"workload": "mean position E[X_T]: release 50 m, U_0 = 0.1 m/s, "
+                                                 "T = 1000 s, M_0 = 40, X_adapt = 50 m, relative eps "
+                                                 + ", ".join(f"{e:g}" for e in ADAPT_EPS_REL)},
+                          "adaptive": rep}), flush=True)
         return
     if args.workload == "batched":
         rep = batched_report(ld, args.steps, args.warmup)

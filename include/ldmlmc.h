@@ -48,7 +48,8 @@ extern "C" {
 #define LD_OK 0
 #define LD_WARN_NOT_CONVERGED 1  /* mlmc_estimate stopped at L_max or max_iter; result filled */
 #define LD_EINVAL (-1)           /* invalid argument (bad parameter, null pointer, size)    */
-#define LD_EUNSTABLE (-2)        /* symplectic Euler with lambda_max * h >= 2 (Sec. 3.1)     */
+#define LD_EUNSTABLE (-2)        /* symplectic Euler with lambda_max * h >= 2 (Sec. 3.1; with
+                                    adaptive steps lambda(x_adapt) * h >= 2, Sec. 7)         */
 #define LD_ENOMEM (-3)           /* workspace smaller than the *_workspace() size           */
 #define LD_EDEVICE (-4)          /* HIP runtime error; ld_last_error() has the message       */
 #define LD_ENONFINITE (-5)       /* some samples were non-finite (excluded from the sums)    */
@@ -97,7 +98,13 @@ typedef struct {
     double z0, w0;
 } ld_release;
 
-/* One estimation problem. T > 0, M0 >= 1, stream_id < 2^24. */
+/* One estimation problem. T > 0, M0 >= 1, stream_id < 2^24.
+   x_adapt (symplectic Euler only; 0 = uniform steps): adaptive, non-nested timesteps
+   below this reference height, 0 < x_adapt <= H (Sec. 7). A path at X steps
+   h_n = min(h, lambda(x_adapt) / lambda(X) h) from its base step (h_l fine, 2 h_l coarse),
+   rounded down to a whole tick of h_l / 2^20 (at least one) and cut at T; the fine and
+   coarse paths draw from the merged time grid (the adaptive Euler increment of Sec. 7).
+   The stability condition becomes lambda(x_adapt) h < 2. */
 typedef struct {
     ld_profile profile;
     ld_release release;
@@ -106,6 +113,7 @@ typedef struct {
     int32_t M0;
     uint32_t stream_id;
     uint64_t seed;
+    double x_adapt;
 } ld_problem;
 
 /* Compensated sums over the finite samples of one level: index 0 Y_l, 1 Y_l^2,
@@ -210,6 +218,7 @@ typedef struct {
     uint64_t seed;
     int32_t max_iter;        /* default 100 */
     int32_t reserved;
+    double x_adapt;          /* symplectic Euler: adaptive steps below this height (0 = off) */
     double max_fine_steps;   /* cost budget: stop (LD_WARN_NOT_CONVERGED) rather than draw
                                 a batch that would take sum_l N_l M_l above this; the
                                 first batch always runs. 0 = no budget (default) */

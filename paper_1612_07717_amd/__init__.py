@@ -64,7 +64,8 @@ class Release(C.Structure):
 
 class Problem(C.Structure):
     _fields_ = [("profile", Profile), ("release", Release), ("qoi", Qoi), ("T", C.c_double),
-                ("M0", C.c_int32), ("stream_id", C.c_uint32), ("seed", C.c_uint64)]
+                ("M0", C.c_int32), ("stream_id", C.c_uint32), ("seed", C.c_uint64),
+                ("x_adapt", C.c_double)]
 
 
 class LevelSums(C.Structure):
@@ -98,7 +99,7 @@ class EstimateOpts(C.Structure):
                 ("fixed_N", C.c_int32), ("eps_is_relative", C.c_int32), ("N_init", C.c_uint64),
                 ("alpha", C.c_double), ("precision", C.c_int32), ("stream_id", C.c_uint32),
                 ("seed", C.c_uint64), ("max_iter", C.c_int32), ("reserved", C.c_int32),
-                ("max_fine_steps", C.c_double),
+                ("x_adapt", C.c_double), ("max_fine_steps", C.c_double),
                 ("d_workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
                 ("hip_stream", C.c_void_p)]
 
@@ -272,7 +273,7 @@ def make_problem(cfg: dict) -> Problem:
         raise ValueError("the library implements the reflection-aware coupling only")
     return Problem(profile=make_profile(cfg), release=make_release(cfg), qoi=make_qoi(cfg),
                    T=cfg["T"], M0=int(cfg["M0"]), stream_id=int(cfg["stream_id"]),
-                   seed=int(cfg["seed"]))
+                   seed=int(cfg["seed"]), x_adapt=float(cfg.get("x_adapt", 0.0)))
 
 
 def sums_to_dict(s: LevelSums) -> dict:
@@ -377,6 +378,7 @@ def estimate_opts(cfg, *, precision="fp64", L_min=2, L_max=20, fixed_L=-1, fixed
     o.seed = int(cfg["seed"])
     o.max_iter = int(max_iter)
     o.max_fine_steps = float(max_fine_steps)
+    o.x_adapt = float(cfg.get("x_adapt", 0.0))
     if workspace is not None:
         o.d_workspace = workspace.data_ptr()
         o.workspace_bytes = workspace.numel() * workspace.element_size()

@@ -13,9 +13,6 @@ namespace ldm {
 namespace {
 thread_local std::string g_last_error;
 
-// Blocks targeted per (level, range): enough to fill 256 CUs several times over so the
-// tail of a launch is short, while each lane gets more samples as n grows.
-constexpr uint64_t kTargetBlocks = 32768;
 
 bool finite(double v) { return std::isfinite(v); }
 }  // namespace
@@ -37,6 +34,12 @@ double lambda_max(const ld_profile& prof) {
     if (prof.kind == LD_PROFILE_HOMOGENEOUS) return 1.0 / prof.tau;
     // lambda = sigma_U / (kappa_tau X) decreases with X; its maximum is at the cut-off.
     return sigma_u_at(prof, prof.eps_reg) / (prof.kappa_tau * prof.eps_reg);
+}
+
+double lambda_at(const ld_profile& prof, double x) {
+    if (prof.kind == LD_PROFILE_HOMOGENEOUS) return 1.0 / prof.tau;
+    const double xc = std::min(std::max(x, prof.eps_reg), prof.H - prof.eps_reg);
+    return sigma_u_at(prof, xc) / (prof.kappa_tau * xc);
 }
 
 int validate_problem(const ld_problem* p) {
@@ -75,16 +78,24 @@ int validate_problem(const ld_problem* p) {
     if (!(finite(p->T) && p->T > 0)) return fail(LD_EINVAL, "T must be positive");
     if (p->M0 < 1) return fail(LD_EINVAL, "M0 must be >= 1");
     if (p->stream_id >= (1u << 24)) return fail(LD_EINVAL, "stream_id must be < 2^24");
+    if (!(finite(p->x_adapt) && p->x_adapt >= 0.0 && p->x_adapt <= f.H))
+        return fail(LD_EINVAL, "x_adapt must lie in [0, H] (0: uniform steps)");
     return LD_OK;
 }
 
 int check_stability(const ld_problem* p, ld_integrator integ, int32_t level) {
+    if (p->x_adapt > 0.0 && integ != LD_SE)
+        return fail(LD_EINVAL, "adaptive steps (x_adapt > 0) are defined for symplectic Euler only");
+    if (p->x_adapt > 0.0 && lambda_max(p->profile) > 64.0 * lambda_at(p->profile, p->x_adapt))
+        return fail(LD_EINVAL, "x_adapt too high: steps would shrink more than 64 times");
     if (integ != LD_SE) return LD_OK;
-    // the longest step of the level: h_0 on level 0, the coarse step 2 h_l above it
+    // the longest step of the level: h_0 on level 0, the coarse step 2 h_l above it; with
+    // adaptive steps lambda h never exceeds lambda(x_adapt) h (Sec. 7)
     const double M = std::ldexp((double)p->M0, level);
     const double h = (level == 0) ? p->T / M : 2.0 * p->T / M;
-    if (lambda_max(p->profile) * h >= 2.0)
-        return fail(LD_EUNSTABLE, "symplectic Euler unstable: lambda_max * h >= 2 (use a larger M0)");
+    const double lam = (p->x_adapt > 0.0) ? lambda_at(p->profile, p->x_adapt) : lambda_max(p->profile);
+    if (lam * h >= 2.0)
+        return fail(LD_EUNSTABLE, "symplectic Euler unstable: lambda * h >= 2 (use a larger M0 or adapt)");
     return LD_OK;
 }
 
@@ -126,17 +137,21 @@ int make_kproblem(const ld_problem* p, ld_integrator integ, KProblem* kp) {
         kp->ncoef = p->qoi.r + 2;
     }
     kp->integ = (int32_t)integ;
+    // In homogeneous turbulence lambda is the same everywhere, so no step ever shortens and
+    // the adaptive scheme is the uniform one: it runs as such.
+    kp->adaptive = (integ == LD_SE && p->x_adapt > 0.0 && kp->profile == KPROFILE_NEUTRAL) ? 1 : 0;
+    kp->x_adapt = p->x_adapt;
     kp->M0 = p->M0;
     kp->stream_id = p->stream_id;
     kp->seed = p->seed;
     return LD_OK;
 }
 
-void plan_item(uint64_t n_samples, uint32_t* spl, uint32_t* n_blocks) {
+void plan_item(uint64_t n_samples, uint32_t* spl, uint32_t* n_blocks, uint64_t target_blocks) {
     const uint64_t per_block = (uint64_t)kBlock;
     uint64_t s = 1;
-    if (n_samples > per_block * kTargetBlocks)
-        s = (n_samples + per_block * kTargetBlocks - 1) / (per_block * kTargetBlocks);
+    if (n_samples > per_block * target_blocks)
+        s = (n_samples + per_block * target_blocks - 1) / (per_block * target_blocks);
     *spl = (uint32_t)s;
     *n_blocks = (uint32_t)((n_samples + per_block * s - 1) / (per_block * s));
 }
@@ -180,17 +195,22 @@ int build_batch(const ld_problem* p, ld_integrator integ, ld_precision prec,
             return fail(LD_EINVAL, "sample range overflows 64 bits");
         rc = check_stability(p, integ, r.level);
         if (rc != LD_OK) return rc;
+        if (args->prob.adaptive && std::ldexp((double)p->M0, r.level) > 67108864.0)
+            return fail(LD_EINVAL, "adaptive steps need M0 * 2^level <= 2^26");
         KItem& it = args->items[j];
         it.level = r.level;
         const uint64_t M = (uint64_t)p->M0 << r.level;
-        if (r.level >= 1 && r.n_samples <= kPipeMaxSamples && M >= kPipeMinSteps) {
+        if (r.level >= 1 && r.n_samples <= kPipeMaxSamples && M >= kPipeMinSteps && !args->prob.adaptive) {
             // long paths and few samples: latency-bound, use the wave-specialised blocks
             it.mode = KMODE_PIPE;
             it.spl = 1;
             it.n_blocks = (uint32_t)((r.n_samples + 63) / 64);
         } else {
             it.mode = KMODE_STREAM;
-            plan_item(r.n_samples, &it.spl, &it.n_blocks);
+            // adaptive paths differ in length: several samples per lane, taken back to back,
+            // even out the work of the lanes of a wave
+            plan_item(r.n_samples, &it.spl, &it.n_blocks,
+                      args->prob.adaptive ? kAdaptiveTargetBlocks : kTargetBlocks);
         }
         it.prio = (uint16_t)std::max(0, 3 - (top_level - r.level));
         it.block_begin = (uint32_t)blocks;

@@ -45,6 +45,8 @@ struct Math<float> {
     static __device__ __forceinline__ float flip(float v, uint32_t mask) {
         return __uint_as_float(__float_as_uint(v) ^ mask);
     }
+    static __device__ __forceinline__ float quot(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+    static __device__ __forceinline__ float floor_(float x) { return __builtin_floorf(x); }
     // v_med3_f32: the median of (x, lo, hi) is x clamped to [lo, hi] for lo <= hi
     static __device__ __forceinline__ float clamp_(float x, float lo, float hi) {
         return __builtin_amdgcn_fmed3f(x, lo, hi);
@@ -101,6 +103,8 @@ struct Math<double> {
     static __device__ __forceinline__ double flip(double v, uint32_t mask) {
         return __hiloint2double(__double2hiint(v) ^ (int)mask, __double2loint(v));
     }
+    static __device__ __forceinline__ double quot(double a, double b) { return a / b; }
+    static __device__ __forceinline__ double floor_(double x) { return floor(x); }
     static __device__ __forceinline__ double expm1_(double x) { return expm1(x); }
     // expm1(z) for |z| <= kSmallZ: the Taylor series to degree 7 (truncation below
     // 1e-17 relative) in Estrin form:
@@ -371,6 +375,77 @@ __device__ __forceinline__ void run_paths(const Consts<R>& c, const Stream& st, 
         R unused_t, unused_w;
         step<R, INTEG, PROF, true, SMALL>(c, g, h2, h, xi_c, unused_t, unused_w);
     }
+}
+
+// ---------------------------------------------------------------------------------
+// Adaptive, non-nested symplectic Euler (Sec. 7). Time is counted in ticks of
+// h_l / 2^kTickBits. A path at X takes h_n = min(h, lambda(x_adapt) / lambda(X) h) from its
+// base step (2^kTickBits ticks fine, twice that coarse), rounded down to whole ticks (at
+// least one) and cut at T. The rule is evaluated in the path precision. Merged-grid
+// interval j draws xi_j (draw j mod 2 of Philox block j / 2, the uniform scheme's
+// mapping); the fine path's increment over its step is the sum of xi_j sqrt(dtau_j), the
+// coarse path's S_c times the sum of S_f xi_j sqrt(dtau_j), S_f taken at the start of
+// interval j.
+//
+// A lane advances its two paths one step per iteration, the one whose step ends first
+// (the fine one on a tie), so every iteration does the work of one step whichever path
+// it belongs to; the loop itself lives with the kernel, which also moves a lane on to its
+// next sample as soon as the current one ends.
+// ---------------------------------------------------------------------------------
+constexpr int kTickBits = 20;
+
+// sigma_U, lambda and the drift coefficients at a path's position, kept with the path:
+// the step rule needs lambda right after a step, and the path's next step needs all four.
+template <typename R>
+struct ACoef {
+    R su, lam, a, b;
+};
+
+template <typename R, int PROF>
+__device__ __forceinline__ ACoef<R> acoef_at(const Consts<R>& c, R x) {
+    ACoef<R> k;
+    if (PROF == KPROFILE_HOMOGENEOUS) {
+        k.su = c.su_h;
+        k.lam = c.lam_h;
+        k.a = (R)0;
+        k.b = (R)0;
+    } else {
+        const R xc = Math<R>::clamp_(x, c.eps, c.Hme);
+        const R d = c.H - xc;
+        R sqd, invd;
+        Math<R>::sqrt_and_rcp(d, sqd, invd);
+        const R r = Math<R>::sqrt_(d * sqd);                 // (H - X_c)^(3/4)
+        k.su = c.ksH * r;
+        k.lam = (c.kl * r) * Math<R>::rcp(xc);
+        const bool inside = (x >= c.eps) && (x <= c.Hme);
+        k.a = inside ? c.acoef_h * sqd : (R)0;
+        k.b = inside ? (R)0.75 * invd : (R)0;
+    }
+    return k;
+}
+
+// End (in ticks) of the step that starts at tick t for a path with lambda = lam: the base
+// step, shortened to floor(lam_adapt / lam * base) ticks (at least 1) where lam exceeds
+// lam_adapt; a NaN lambda (a run-away path) takes the base step. Steps are at most 2^21
+// ticks; T (the tick counter type) must hold t_end + 2^21.
+template <typename R, typename T>
+__device__ __forceinline__ T adaptive_end(R lam_adapt, R lam, T t, uint32_t base, T t_end) {
+    uint32_t k = base;
+    if (lam > lam_adapt) {
+        const R steps = Math<R>::floor_(Math<R>::quot(lam_adapt, lam) * (R)base);
+        k = steps < (R)1 ? 1u : (steps < (R)base ? (uint32_t)steps : base);
+    }
+    return (t + k < t_end) ? t + k : t_end;
+}
+
+// Eq. (8) driven by the Brownian increment dW of the step (dW stands for sqrt(h) xi):
+// U' = (1 - lambda h) U - (a + b U^2) h + sigma dW with sigma = sigma_U sqrt(2 lambda).
+template <typename R>
+__device__ __forceinline__ void se_step_dw(const ACoef<R>& k, R h, R dW, R H, Path<R>& p) {
+    const R sigma = k.su * Math<R>::sqrt_((R)2 * k.lam);
+    p.u = ((R)1 - k.lam * h) * p.u - (k.a + k.b * p.u * p.u) * h + sigma * dW;
+    p.x = p.x + p.u * h;
+    fold(p, H);
 }
 
 // Runs one sample of `level`. Returns the terminal fine and coarse states.

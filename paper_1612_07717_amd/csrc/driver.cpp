@@ -209,6 +209,7 @@ int mlmc_estimate(double eps, const ld_qoi* qoi, ld_integrator integrator, const
     prob.M0 = opts.M0;
     prob.stream_id = opts.stream_id;
     prob.seed = opts.seed;
+    prob.x_adapt = opts.x_adapt;
     int rc = validate_problem(&prob);
     if (rc != LD_OK) return rc;
     const int32_t L0 = opts.fixed_L >= 0 ? opts.fixed_L : opts.L_min;

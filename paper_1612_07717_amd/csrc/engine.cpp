@@ -95,6 +95,8 @@ int validate_query(const ld_query* qq) {
         return fail(LD_EINVAL, "need 0 <= L_min <= L_max < LD_MAX_LEVELS");
     if (qq->N_init < 2) return fail(LD_EINVAL, "N_init must be >= 2");
     if (!(qq->max_fine_steps >= 0.0)) return fail(LD_EINVAL, "max_fine_steps must be >= 0");
+    if (qq->problem.x_adapt > 0.0)
+        return fail(LD_EINVAL, "adaptive steps run through mlmc_estimate, not the engine");
     if (std::ldexp((double)qq->problem.M0, qq->L_max) > 2147483648.0)
         return fail(LD_EINVAL, "M0 * 2^L_max must not exceed 2^31");
     return check_stability(&qq->problem, qq->integrator, 0);
@@ -128,7 +130,7 @@ void tile_range(const ld_engine* e, uint32_t slot, const Query& qu, int32_t leve
     t.sample_begin = begin;
     t.n_samples = n;
     t.prio = prio;
-    if (level >= 1 && n <= e->opts.pipe_max_samples && M >= e->opts.pipe_min_steps) {
+    if (level >= 1 && n <= e->opts.pipe_max_samples && M >= e->opts.pipe_min_steps && !qu.kp.adaptive) {
         t.mode = KMODE_PIPE;
         t.spl = 1;
         const uint64_t nb = (n + 63) / 64;
@@ -152,7 +154,8 @@ void tile_range(const ld_engine* e, uint32_t slot, const Query& qu, int32_t leve
 
 uint64_t tiles_of_range(const ld_engine* e, const Query& qu, int32_t level, uint64_t n) {
     const uint64_t M = (uint64_t)qu.prob.M0 << level;
-    if (level >= 1 && n <= e->opts.pipe_max_samples && M >= e->opts.pipe_min_steps) return (n + 63) / 64;
+    if (level >= 1 && n <= e->opts.pipe_max_samples && M >= e->opts.pipe_min_steps && !qu.kp.adaptive)
+        return (n + 63) / 64;
     const uint64_t per = (uint64_t)kBlock;
     const uint64_t T = std::max<uint64_t>(1, e->opts.target_tiles);
     const uint64_t spl = (n > per * T) ? (n + per * T - 1) / (per * T) : 1;

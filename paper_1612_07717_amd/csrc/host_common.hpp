@@ -7,6 +7,12 @@
 
 namespace ldm {
 
+// Blocks targeted per (level, range): enough to fill 256 CUs several times over so the
+// tail of a launch is short, while each lane gets more samples as n grows. Adaptive
+// steps use fewer blocks and more samples per lane (their paths differ in length).
+constexpr uint64_t kTargetBlocks = 32768;
+constexpr uint64_t kAdaptiveTargetBlocks = 2048;
+
 void set_error(const std::string& msg);
 int fail(int status, const std::string& msg);
 
@@ -32,6 +38,8 @@ int check_stability(const ld_problem* p, ld_integrator integ, int32_t level);
 double sigma_u_at(const ld_profile& prof, double x);
 // lambda_max over [0, H].
 double lambda_max(const ld_profile& prof);
+// lambda = 1/tau at x (regularised, Eqs. 5, 7).
+double lambda_at(const ld_profile& prof, double x);
 
 // Fills the kernel-side problem (FP64 parameters, smoothing coefficients).
 int make_kproblem(const ld_problem* p, ld_integrator integ, KProblem* kp);
@@ -40,7 +48,7 @@ int make_kproblem(const ld_problem* p, ld_integrator integ, KProblem* kp);
 int smoothing_coefficients(int r, double* coef);
 
 // Launch plan of one (level, range): samples per lane and block count.
-void plan_item(uint64_t n_samples, uint32_t* spl, uint32_t* n_blocks);
+void plan_item(uint64_t n_samples, uint32_t* spl, uint32_t* n_blocks, uint64_t target_blocks = kTargetBlocks);
 // Upper bound of the blocks any level's range of n_samples uses (either block mode).
 uint32_t max_blocks(uint64_t n_samples);
 

@@ -309,6 +309,152 @@ __device__ __forceinline__ void set_priority(uint32_t prio) {
     }
 }
 
+// The samples of one lane with adaptive symplectic Euler steps (Sec. 7): samples
+// base + k kBlock + lane for k = 0 .. spl - 1 inside the range, in that order, each
+// accumulated as it ends, as in the fixed-step loop. The loop is flat: a lane whose sample
+// ends starts its next one in the same loop, so lanes whose paths took fewer steps do not
+// wait for the longest path of the wave before they go on.
+//
+// Normals: interval j takes normal j of the sample's stream (component j mod 2 of Philox
+// block j / 2). A lane uses at most one per iteration; it keeps up to three in a queue and
+// refills it (one block, two normals) only on its even iterations, when fewer than two
+// are left, so the lanes of a wave generate blocks together on every other iteration
+// instead of each on its own. A new sample enters with its first block drawn.
+// T: tick counter type, 32 bits when T in ticks fits.
+template <typename R, int PROF, typename T>
+__device__ __forceinline__ void adaptive_lane(const KProblem& kp, const Consts<R>& c, const KItem& item,
+                                              uint64_t first, uint32_t n_mine, Acc& acc, double* dump) {
+    const int level = item.level;
+    const bool coupled = level != 0;
+    const uint64_t M = (uint64_t)kp.M0 << level;                   // M_l = M_0 2^l
+    const uint32_t base = 1u << kTickBits;                         // h_l in ticks
+    const T t_end = (T)(M << kTickBits);                           // T in ticks
+    const R tick = (R)((kp.T / (double)M) / (double)base);
+    // lambda(x_adapt) by the same arithmetic as lambda(X): with x_adapt at the cut-off no
+    // path's lambda exceeds it, and the scheme is the uniform one exactly
+    const R lam_a = acoef_at<R, PROF>(c, (R)kp.x_adapt).lam;
+
+    Stream st = make_stream(kp.seed, kp.stream_id, level, 0);
+    Path<R> f, g;
+    ACoef<R> kf, kg;
+    T tf = 0, tc = 0, ef = 0, ec = 0, tau = 0;
+    uint32_t k = 0, it = 0, blk = 0, cnt = 0;   // it: own iterations; blk: next Philox block
+    R wf = (R)0, wc = (R)0, q0 = (R)0, q1 = (R)0, q2 = (R)0;
+    bool live = n_mine > 0, fresh = true;
+    while (live) {
+        if (fresh) {                         // start sample k of this lane
+            st = make_stream(kp.seed, kp.stream_id, level, item.sample_begin + first + (uint64_t)k * kBlock);
+            R x0, u0;
+            initial_state<R, PROF>(kp, c, st, x0, u0);
+            init_path<R, KINTEG_SE, PROF>(c, f, x0, u0);
+            init_path<R, KINTEG_SE, PROF>(c, g, x0, u0);
+            kf = acoef_at<R, PROF>(c, x0);
+            kg = kf;
+            tf = tc = tau = 0;
+            wf = wc = (R)0;
+            ef = adaptive_end(lam_a, kf.lam, (T)0, base, t_end);
+            ec = coupled ? adaptive_end(lam_a, kg.lam, (T)0, 2u * base, t_end) : t_end;
+            Normals<R>::pair(philox(st, 0u), q0, q1);
+            blk = 1;
+            cnt = 2;
+            fresh = false;
+        }
+        if ((it & 1u) == 0u && cnt < 2u) {   // refill: append normals 2 blk, 2 blk + 1
+            R a, b;
+            Normals<R>::pair(philox(st, blk), a, b);
+            ++blk;
+            if (cnt == 0u) q0 = a;
+            q1 = (cnt == 0u) ? b : a;
+            q2 = b;
+            cnt += 2u;
+        }
+        ++it;
+        // the next event: the end of the fine step or of the coarse step, fine first on a tie
+        const bool fine_ev = (tf < t_end) && (!coupled || ef <= ec);
+        const T e = fine_ev ? ef : ec;
+        if (e > tau) {                       // merged interval [tau, e] takes the next normal
+            const R dW = q0 * Math<R>::sqrt_((R)(uint32_t)(e - tau) * tick);
+            q0 = q1;
+            q1 = q2;
+            --cnt;
+            wf += dW;
+            wc += Math<R>::flip(dW, f.sgn);  // S_f at the start of the interval
+            tau = e;
+        }
+        // one step of the path whose step ends at e, field by field (no path copies)
+        Path<R> p;
+        p.x = fine_ev ? f.x : g.x;
+        p.u = fine_ev ? f.u : g.u;
+        p.sgn = fine_ev ? f.sgn : g.sgn;
+        p.bad = fine_ev ? f.bad : g.bad;
+        p.a = (R)0;
+        p.b = (R)0;
+        ACoef<R> kc;
+        kc.su = fine_ev ? kf.su : kg.su;
+        kc.lam = fine_ev ? kf.lam : kg.lam;
+        kc.a = fine_ev ? kf.a : kg.a;
+        kc.b = fine_ev ? kf.b : kg.b;
+        const R h = (R)(uint32_t)(e - (fine_ev ? tf : tc)) * tick;
+        const R dW = fine_ev ? wf : Math<R>::flip(wc, g.sgn);
+        se_step_dw(kc, h, dW, c.H, p);
+        const ACoef<R> kn = acoef_at<R, PROF>(c, p.x);
+        const T en = adaptive_end(lam_a, kn.lam, e, fine_ev ? base : 2u * base, t_end);
+        f.x = fine_ev ? p.x : f.x;
+        f.u = fine_ev ? p.u : f.u;
+        f.sgn = fine_ev ? p.sgn : f.sgn;
+        f.bad = fine_ev ? p.bad : f.bad;
+        g.x = fine_ev ? g.x : p.x;
+        g.u = fine_ev ? g.u : p.u;
+        g.sgn = fine_ev ? g.sgn : p.sgn;
+        g.bad = fine_ev ? g.bad : p.bad;
+        kf.su = fine_ev ? kn.su : kf.su;
+        kf.lam = fine_ev ? kn.lam : kf.lam;
+        kf.a = fine_ev ? kn.a : kf.a;
+        kf.b = fine_ev ? kn.b : kf.b;
+        kg.su = fine_ev ? kg.su : kn.su;
+        kg.lam = fine_ev ? kg.lam : kn.lam;
+        kg.a = fine_ev ? kg.a : kn.a;
+        kg.b = fine_ev ? kg.b : kn.b;
+        tf = fine_ev ? e : tf;
+        ef = fine_ev ? en : ef;
+        wf = fine_ev ? (R)0 : wf;
+        tc = fine_ev ? tc : e;
+        ec = fine_ev ? ec : en;
+        wc = fine_ev ? wc : (R)0;
+        if (tf == t_end && (!coupled || tc == t_end)) {
+            const double pf = qoi(kp, (double)f.x, (double)f.u);
+            const double pc = coupled ? qoi(kp, (double)g.x, (double)g.u) : 0.0;
+            const bool bad = f.bad || (coupled && g.bad) || !isfinite(pf) || !isfinite(pc);
+            if (dump != nullptr) {
+                const uint64_t local = first + (uint64_t)k * kBlock;
+                dump[2 * local] = pf;
+                dump[2 * local + 1] = pc;
+            }
+            accumulate(acc, pf, pc, bad);
+            ++k;
+            live = k < n_mine;
+            fresh = true;
+        }
+    }
+}
+
+// The lane's share of an adaptive item; 32-bit tick counters where T in ticks plus the
+// longest step (2^21 ticks) fits.
+template <typename R, int PROF>
+__device__ __forceinline__ void adaptive_samples(const KProblem& kp, const Consts<R>& c, const KItem& item,
+                                                 uint32_t local_block, Acc& acc, double* dump) {
+    const uint64_t first = (uint64_t)local_block * (uint64_t)kBlock * item.spl + threadIdx.x;
+    uint32_t n_mine = 0;
+    if (first < item.n_samples) {
+        const uint64_t left = (item.n_samples - first + kBlock - 1) / kBlock;
+        n_mine = left < (uint64_t)item.spl ? (uint32_t)left : item.spl;
+    }
+    if (((uint64_t)kp.M0 << (item.level + kTickBits)) + ((uint64_t)2 << kTickBits) < ((uint64_t)1 << 32))
+        adaptive_lane<R, PROF, uint32_t>(kp, c, item, first, n_mine, acc, dump);
+    else
+        adaptive_lane<R, PROF, uint64_t>(kp, c, item, first, n_mine, acc, dump);
+}
+
 // The work of one block: block `local_block` of `item`, in the item's mode. acc receives
 // this block's sums (valid in thread 0 after block_reduce).
 template <typename R, int INTEG, int PROF>
@@ -316,7 +462,9 @@ __device__ __forceinline__ void run_block(const KProblem& kp, const KItem& item,
                                           uint32_t local_block, Acc& acc, double* dump,
                                           PipeLds<R>& lds) {
     const Consts<R> c = make_consts<R>(kp);
-    if (item.mode == KMODE_PIPE) {
+    if constexpr (INTEG == KINTEG_SE_ADAPT) {    // STREAM layout; PIPE is never chosen for it
+        adaptive_samples<R, PROF>(kp, c, item, local_block, acc, dump);
+    } else if (item.mode == KMODE_PIPE) {
         pipe_samples<R, INTEG, PROF>(kp, c, item, local_block, acc, dump, lds);
     } else {
         const uint64_t base = (uint64_t)local_block * (uint64_t)kBlock * item.spl;
@@ -576,7 +724,8 @@ int launch_pdf_bins(const KBins& bins, const KProblem& kp, const double* d_dump,
 using LevelKernel = void (*)(const KArgs, ld_level_sums*, double*);
 
 template <typename R>
-LevelKernel pick_kernel(int integ, int profile) {
+LevelKernel pick_kernel(int integ, int profile, bool adaptive) {
+    if (adaptive) return level_kernel<R, KINTEG_SE_ADAPT, KPROFILE_NEUTRAL>;   // neutral only
     switch (integ * 2 + profile) {
         case KINTEG_SE * 2 + KPROFILE_HOMOGENEOUS: return level_kernel<R, KINTEG_SE, KPROFILE_HOMOGENEOUS>;
         case KINTEG_SE * 2 + KPROFILE_NEUTRAL: return level_kernel<R, KINTEG_SE, KPROFILE_NEUTRAL>;
@@ -592,8 +741,8 @@ int launch_levels(const KArgs& args, uint32_t total_blocks, ld_level_sums* d_par
     hipStream_t s = (hipStream_t)stream;
     if (total_blocks > 0) {
         const LevelKernel k = (args.precision == LD_FP32)
-                                  ? pick_kernel<float>(args.prob.integ, args.prob.profile)
-                                  : pick_kernel<double>(args.prob.integ, args.prob.profile);
+                                  ? pick_kernel<float>(args.prob.integ, args.prob.profile, args.prob.adaptive)
+                                  : pick_kernel<double>(args.prob.integ, args.prob.profile, args.prob.adaptive);
         hipLaunchKernelGGL(k, dim3(total_blocks), dim3(kBlock), 0, s, args, d_partials, d_dump);
         if (hipGetLastError() != hipSuccess) return LD_EDEVICE;
     }

@@ -8,7 +8,8 @@
 
 namespace ldm {
 
-enum { KINTEG_SE = 0, KINTEG_GL = 1, KINTEG_BAOAB = 2 };
+enum { KINTEG_SE = 0, KINTEG_GL = 1, KINTEG_BAOAB = 2,
+       KINTEG_SE_ADAPT = 3 };   // kernel variant: symplectic Euler with adaptive steps (Sec. 7)
 enum { KPROFILE_HOMOGENEOUS = 0, KPROFILE_NEUTRAL = 1 };
 enum { KRELEASE_FIXED_W = 0, KRELEASE_GAUSSIAN_W = 1, KRELEASE_WELL_MIXED = 2 };
 enum { KQOI_MEAN_Z = 0, KQOI_P_ABOVE = 1, KQOI_P_BOX = 2, KQOI_VELOCITY = 3, KQOI_VELOCITY_SQ = 4 };
@@ -33,9 +34,10 @@ struct KProblem {
     double z0, w0, su_z0;          // release; su_z0 = regularised sigma_U(z0)
     double lam_max;                // max of lambda = 1/tau over [0, H]
     double ksH, kl;                // kappa_sigma u_* H^(-3/4) and ksH / kappa_tau
+    double x_adapt;                // adaptive symplectic Euler: reference height (0: uniform)
     double qa, qb, inv_delta;
     double coef[kMaxCoef];
-    int32_t integ, profile, release, qoi_kind, r, ncoef, M0;
+    int32_t integ, profile, release, qoi_kind, r, ncoef, M0, adaptive;
     uint32_t stream_id;
     uint64_t seed;
 };

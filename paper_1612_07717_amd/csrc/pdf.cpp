@@ -235,6 +235,7 @@ int mlmc_estimate_pdf(double eps, const ld_bins* bins, const ld_qoi* qoi, ld_int
     prob.M0 = opts.M0;
     prob.stream_id = opts.stream_id;
     prob.seed = opts.seed;
+    prob.x_adapt = opts.x_adapt;
     if (estimator == LD_STMC) {
         if (opts.fixed_L < 0 || opts.fixed_L >= LD_MAX_LEVELS) return fail(LD_EINVAL, "StMC needs 0 <= fixed_L");
         if (std::ldexp((double)opts.M0, opts.fixed_L) > 2147483648.0)

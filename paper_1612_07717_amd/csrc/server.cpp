@@ -173,6 +173,7 @@ void worker_fifo(ld_server* s) {
         o.seed = q.problem.seed;
         o.max_iter = q.max_iter > 0 ? q.max_iter : 100;
         o.max_fine_steps = q.max_fine_steps;
+        o.x_adapt = q.problem.x_adapt;
         o.d_workspace = s->d_ws;
         o.workspace_bytes = mlmc_estimate_workspace();
         o.hip_stream = s->stream;

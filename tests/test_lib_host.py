@@ -262,3 +262,21 @@ def test_pdf_arguments_rejected_without_device(lib):
                                  0, C.byref(res)) == ld.LD_EINVAL       # absolute eps only
     assert lib.mlmc_estimate_pdf(1e-3, C.byref(good), C.byref(q), 1, C.byref(prof), C.byref(o),
                                  5, C.byref(res)) == ld.LD_EINVAL       # unknown estimator
+
+
+def test_adaptive_steps_validation_and_stability(lib):
+    """x_adapt > 0 selects the adaptive symplectic Euler of Sec. 7: SE only, the
+    stability condition uses lambda(x_adapt) (dt_0 = T/8 becomes stable with x_adapt =
+    50 m), and the engine leaves such queries to mlmc_estimate."""
+    se8 = W.single_large("SE")                                   # M0 = 8: lambda_max h_0 = 6.45
+    assert _call_level_sums(lib, se8, level=0) == ld.LD_EUNSTABLE
+    ada = dict(se8, x_adapt=50.0)                                # lambda(50 m) h_0 = 1.25
+    assert _call_level_sums(lib, ada, level=0, ws_bytes=0) == ld.LD_ENOMEM
+    assert _call_level_sums(lib, dict(ada, integrator="GL"), level=0) == ld.LD_EINVAL
+    assert _call_level_sums(lib, dict(ada, x_adapt=-1.0), level=0) == ld.LD_EINVAL
+    assert _call_level_sums(lib, dict(ada, x_adapt=2000.0), level=0) == ld.LD_EINVAL
+    assert _call_level_sums(lib, dict(ada, x_adapt=900.0), level=0) == ld.LD_EINVAL   # > 64x shorter steps
+    assert _call_level_sums(lib, dict(ada, M0=1 << 20), level=7) == ld.LD_EINVAL      # M > 2^26
+    q = ld.make_query(ada, 1e-2)
+    res = (ld.EstimateResult * 1)()
+    assert lib.mlmc_estimate_batch((ld.Query * 1)(q), 1, None, res) == ld.LD_EINVAL

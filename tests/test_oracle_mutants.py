@@ -47,7 +47,8 @@ MUTANTS = [
     ("coarse step uses h", "oracle_step(p, 2.0 * h, coarse", "oracle_step(p, h, coarse"),
     ("coarse noise without S_c", "double physical = noise_is_tilde ? s * xi : xi;",
      "double physical = xi;"),
-    ("h_l off by one step", "double h = p->T / (double)M;", "double h = p->T / (double)(M + 1);"),
+    ("h_l off by one step", "double h = p->T / (double)M;               /* h_l = T / M_l */",
+     "double h = p->T / (double)(M + 1);"),
     ("Y_l = P_l + P_{l-1}", "double y = pf - pc;", "double y = pf + pc;"),
     ("Box-Muller radius", "sqrt(-2.0 * log(u))", "sqrt(-log(u))"),
     ("Box-Muller pair both cosines", "out[1] = rho * sin(theta);", "out[1] = rho * cos(theta);"),
@@ -59,13 +60,21 @@ MUTANTS = [
     ("smoothing moment sign", "a[2 + j][n] = ((j % 2 == 0) ? 1.0L : -1.0L)", "a[2 + j][n] = (1.0L)"),
     ("box indicator reversed", "return theta(x - p->qb) - theta(x - p->qa);",
      "return theta(x - p->qa) - theta(x - p->qb);"),
+    ("adaptive coarse increment without S^(f)", "wc += (naive ? 1.0 : fine[2]) * dW;",
+     "wc += dW;"),
+    ("adaptive step ratio inverted", "double ratio = lam_adapt / lambda;",
+     "double ratio = lambda / lam_adapt;"),
+    ("adaptive coarse base step h", "ec = adaptive_end(p, lam_adapt, coarse[0], tc, 2 * tick_base",
+     "ec = adaptive_end(p, lam_adapt, coarse[0], tc, tick_base"),
+    ("adaptive increment without the square root", "z[j % 2] * sqrt((double)(next - tau) * tick)",
+     "z[j % 2] * ((double)(next - tau) * tick)"),
     ("Gaussian release uses sigma_U(0)", "oracle_profile(p, p->z0, &su, &tau);\n            oracle_normals",
      "oracle_profile(p, 0.0, &su, &tau);\n            oracle_normals"),
 ]
 
 PIN_FILES = ["test_oracle_rng.py", "test_oracle_model.py", "test_oracle_closed_forms.py",
              "test_oracle_coupling.py", "test_oracle_smoothing_sums_driver.py",
-             "test_oracle_paper_values.py"]
+             "test_oracle_paper_values.py", "test_oracle_adaptive.py"]
 
 
 def _run_mutant(args):
