@@ -207,10 +207,9 @@ int build_batch(const ld_problem* p, ld_integrator integ, ld_precision prec,
             it.n_blocks = (uint32_t)((r.n_samples + 63) / 64);
         } else {
             it.mode = KMODE_STREAM;
-            // adaptive paths differ in length: several samples per lane, taken back to back,
-            // even out the work of the lanes of a wave
-            plan_item(r.n_samples, &it.spl, &it.n_blocks,
-                      args->prob.adaptive ? kAdaptiveTargetBlocks : kTargetBlocks);
+            const uint64_t target = !args->prob.adaptive ? kTargetBlocks
+                                    : (prec == LD_FP32 ? kAdaptiveTargetBlocksFp32 : kAdaptiveTargetBlocksFp64);
+            plan_item(r.n_samples, &it.spl, &it.n_blocks, target);
         }
         it.prio = (uint16_t)std::max(0, 3 - (top_level - r.level));
         it.block_begin = (uint32_t)blocks;

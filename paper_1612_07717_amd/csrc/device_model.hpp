@@ -392,7 +392,7 @@ __device__ __forceinline__ void run_paths(const Consts<R>& c, const Stream& st, 
 // it belongs to; the loop itself lives with the kernel, which also moves a lane on to its
 // next sample as soon as the current one ends.
 // ---------------------------------------------------------------------------------
-constexpr int kTickBits = 20;
+constexpr int kTickBits = kAdaptTickBits;
 
 // sigma_U, lambda and the drift coefficients at a path's position, kept with the path:
 // the step rule needs lambda right after a step, and the path's next step needs all four.

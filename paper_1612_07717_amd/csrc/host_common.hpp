@@ -9,9 +9,12 @@ namespace ldm {
 
 // Blocks targeted per (level, range): enough to fill 256 CUs several times over so the
 // tail of a launch is short, while each lane gets more samples as n grows. Adaptive
-// steps use fewer blocks and more samples per lane (their paths differ in length).
+// steps use one resident round of blocks (5 per CU in FP32, 3 in FP64, as their register
+// use allows) with as many samples per wave as that leaves: their paths differ in length,
+// and a wave's tail is shorter relative to a longer chunk.
 constexpr uint64_t kTargetBlocks = 32768;
-constexpr uint64_t kAdaptiveTargetBlocks = 2048;
+constexpr uint64_t kAdaptiveTargetBlocksFp32 = 1280;
+constexpr uint64_t kAdaptiveTargetBlocksFp64 = 768;
 
 void set_error(const std::string& msg);
 int fail(int status, const std::string& msg);

@@ -309,11 +309,14 @@ __device__ __forceinline__ void set_priority(uint32_t prio) {
     }
 }
 
-// The samples of one lane with adaptive symplectic Euler steps (Sec. 7): samples
-// base + k kBlock + lane for k = 0 .. spl - 1 inside the range, in that order, each
-// accumulated as it ends, as in the fixed-step loop. The loop is flat: a lane whose sample
-// ends starts its next one in the same loop, so lanes whose paths took fewer steps do not
-// wait for the longest path of the wave before they go on.
+// One wave's samples with adaptive symplectic Euler steps (Sec. 7): the contiguous chunk
+// [c_begin, c_end) of the item's range. Adaptive paths differ in length, so samples are
+// handed out as lanes free up: every iteration the wave counts (ballot) the lanes whose
+// sample ended, gives them the next indices of the chunk in lane order and moves its
+// shared cursor on. A wave runs in lockstep, so the assignment, and with it each lane's
+// order of accumulation, is a function of the inputs alone: results are reproducible
+// bit for bit. The loop is flat: a lane finishes one sample and starts the next in the
+// same iteration, and lanes go idle only once the chunk is used up.
 //
 // Normals: interval j takes normal j of the sample's stream (component j mod 2 of Philox
 // block j / 2). A lane uses at most one per iteration; it keeps up to three in a queue and
@@ -323,7 +326,7 @@ __device__ __forceinline__ void set_priority(uint32_t prio) {
 // T: tick counter type, 32 bits when T in ticks fits.
 template <typename R, int PROF, typename T>
 __device__ __forceinline__ void adaptive_lane(const KProblem& kp, const Consts<R>& c, const KItem& item,
-                                              uint64_t first, uint32_t n_mine, Acc& acc, double* dump) {
+                                              uint64_t c_begin, uint64_t c_end, Acc& acc, double* dump) {
     const int level = item.level;
     const bool coupled = level != 0;
     const uint64_t M = (uint64_t)kp.M0 << level;                   // M_l = M_0 2^l
@@ -338,12 +341,34 @@ __device__ __forceinline__ void adaptive_lane(const KProblem& kp, const Consts<R
     Path<R> f, g;
     ACoef<R> kf, kg;
     T tf = 0, tc = 0, ef = 0, ec = 0, tau = 0;
-    uint32_t k = 0, it = 0, blk = 0, cnt = 0;   // it: own iterations; blk: next Philox block
+    uint32_t it = 0, blk = 0, cnt = 0;   // it: own iterations; blk: next Philox block
     R wf = (R)0, wc = (R)0, q0 = (R)0, q1 = (R)0, q2 = (R)0;
-    bool live = n_mine > 0, fresh = true;
-    while (live) {
-        if (fresh) {                         // start sample k of this lane
-            st = make_stream(kp.seed, kp.stream_id, level, item.sample_begin + first + (uint64_t)k * kBlock);
+    uint64_t cur = 0, cursor = c_begin;  // the lane's sample; the wave's next free index
+    bool fresh = true;
+    for (;;) {
+        // hand the next indices of the chunk to the lanes whose sample ended (all lanes
+        // still in the loop take part, so every copy of the cursor stays the same)
+        const bool need = fresh || (tf == t_end && (!coupled || tc == t_end));
+        const uint64_t mask = __ballot(need);
+        const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+        const uint64_t mine = cursor + rank;
+        cursor += (uint64_t)__popcll(mask);
+        // one divergent branch per iteration: finish the sample that ended, start the next
+        if (need) {
+            if (!fresh) {
+                const double pf = qoi(kp, (double)f.x, (double)f.u);
+                const double pc = coupled ? qoi(kp, (double)g.x, (double)g.u) : 0.0;
+                const bool bad = f.bad || (coupled && g.bad) || !isfinite(pf) || !isfinite(pc);
+                if (dump != nullptr) {
+                    dump[2 * cur] = pf;
+                    dump[2 * cur + 1] = pc;
+                }
+                accumulate(acc, pf, pc, bad);
+            }
+            if (mine >= c_end) break;
+            cur = mine;
+            st = make_stream(kp.seed, kp.stream_id, level, item.sample_begin + cur);
             R x0, u0;
             initial_state<R, PROF>(kp, c, st, x0, u0);
             init_path<R, KINTEG_SE, PROF>(c, f, x0, u0);
@@ -372,15 +397,16 @@ __device__ __forceinline__ void adaptive_lane(const KProblem& kp, const Consts<R
         // the next event: the end of the fine step or of the coarse step, fine first on a tie
         const bool fine_ev = (tf < t_end) && (!coupled || ef <= ec);
         const T e = fine_ev ? ef : ec;
-        if (e > tau) {                       // merged interval [tau, e] takes the next normal
-            const R dW = q0 * Math<R>::sqrt_((R)(uint32_t)(e - tau) * tick);
-            q0 = q1;
-            q1 = q2;
-            --cnt;
-            wf += dW;
-            wc += Math<R>::flip(dW, f.sgn);  // S_f at the start of the interval
-            tau = e;
-        }
+        // a new merged interval [tau, e] takes the next normal; an event at tau (the second
+        // step ending at a shared time point) adds exact zeros
+        const bool adv = e > tau;
+        const R dW = q0 * Math<R>::sqrt_((R)(uint32_t)(e - tau) * tick);
+        q0 = adv ? q1 : q0;
+        q1 = adv ? q2 : q1;
+        cnt -= adv ? 1u : 0u;
+        wf += dW;
+        wc += Math<R>::flip(dW, f.sgn);      // S_f at the start of the interval
+        tau = e;
         // one step of the path whose step ends at e, field by field (no path copies)
         Path<R> p;
         p.x = fine_ev ? f.x : g.x;
@@ -395,8 +421,8 @@ __device__ __forceinline__ void adaptive_lane(const KProblem& kp, const Consts<R
         kc.a = fine_ev ? kf.a : kg.a;
         kc.b = fine_ev ? kf.b : kg.b;
         const R h = (R)(uint32_t)(e - (fine_ev ? tf : tc)) * tick;
-        const R dW = fine_ev ? wf : Math<R>::flip(wc, g.sgn);
-        se_step_dw(kc, h, dW, c.H, p);
+        const R dWs = fine_ev ? wf : Math<R>::flip(wc, g.sgn);
+        se_step_dw(kc, h, dWs, c.H, p);
         const ACoef<R> kn = acoef_at<R, PROF>(c, p.x);
         const T en = adaptive_end(lam_a, kn.lam, e, fine_ev ? base : 2u * base, t_end);
         f.x = fine_ev ? p.x : f.x;
@@ -421,38 +447,24 @@ __device__ __forceinline__ void adaptive_lane(const KProblem& kp, const Consts<R
         tc = fine_ev ? tc : e;
         ec = fine_ev ? ec : en;
         wc = fine_ev ? wc : (R)0;
-        if (tf == t_end && (!coupled || tc == t_end)) {
-            const double pf = qoi(kp, (double)f.x, (double)f.u);
-            const double pc = coupled ? qoi(kp, (double)g.x, (double)g.u) : 0.0;
-            const bool bad = f.bad || (coupled && g.bad) || !isfinite(pf) || !isfinite(pc);
-            if (dump != nullptr) {
-                const uint64_t local = first + (uint64_t)k * kBlock;
-                dump[2 * local] = pf;
-                dump[2 * local + 1] = pc;
-            }
-            accumulate(acc, pf, pc, bad);
-            ++k;
-            live = k < n_mine;
-            fresh = true;
-        }
     }
 }
 
-// The lane's share of an adaptive item; 32-bit tick counters where T in ticks plus the
-// longest step (2^21 ticks) fits.
-template <typename R, int PROF>
+// The wave's share of an adaptive item: a chunk of 64 spl samples per wave, in block and
+// wave order. WIDE: 64-bit tick counters (else T in ticks plus the longest step, 2^21
+// ticks, fits 32 bits: the host picks the kernel).
+template <typename R, int PROF, bool WIDE>
 __device__ __forceinline__ void adaptive_samples(const KProblem& kp, const Consts<R>& c, const KItem& item,
                                                  uint32_t local_block, Acc& acc, double* dump) {
-    const uint64_t first = (uint64_t)local_block * (uint64_t)kBlock * item.spl + threadIdx.x;
-    uint32_t n_mine = 0;
-    if (first < item.n_samples) {
-        const uint64_t left = (item.n_samples - first + kBlock - 1) / kBlock;
-        n_mine = left < (uint64_t)item.spl ? (uint32_t)left : item.spl;
-    }
-    if (((uint64_t)kp.M0 << (item.level + kTickBits)) + ((uint64_t)2 << kTickBits) < ((uint64_t)1 << 32))
-        adaptive_lane<R, PROF, uint32_t>(kp, c, item, first, n_mine, acc, dump);
+    const uint64_t chunk = 64ull * item.spl;
+    const uint64_t wave = (uint64_t)local_block * (kBlock / 64) + (threadIdx.x >> 6);
+    const uint64_t c_begin = wave * chunk;
+    if (c_begin >= item.n_samples) return;
+    const uint64_t c_end = (c_begin + chunk < item.n_samples) ? c_begin + chunk : item.n_samples;
+    if constexpr (WIDE)
+        adaptive_lane<R, PROF, uint64_t>(kp, c, item, c_begin, c_end, acc, dump);
     else
-        adaptive_lane<R, PROF, uint64_t>(kp, c, item, first, n_mine, acc, dump);
+        adaptive_lane<R, PROF, uint32_t>(kp, c, item, c_begin, c_end, acc, dump);
 }
 
 // The work of one block: block `local_block` of `item`, in the item's mode. acc receives
@@ -462,8 +474,8 @@ __device__ __forceinline__ void run_block(const KProblem& kp, const KItem& item,
                                           uint32_t local_block, Acc& acc, double* dump,
                                           PipeLds<R>& lds) {
     const Consts<R> c = make_consts<R>(kp);
-    if constexpr (INTEG == KINTEG_SE_ADAPT) {    // STREAM layout; PIPE is never chosen for it
-        adaptive_samples<R, PROF>(kp, c, item, local_block, acc, dump);
+    if constexpr (INTEG == KINTEG_SE_ADAPT || INTEG == KINTEG_SE_ADAPT_WIDE) {   // STREAM layout only
+        adaptive_samples<R, PROF, INTEG == KINTEG_SE_ADAPT_WIDE>(kp, c, item, local_block, acc, dump);
     } else if (item.mode == KMODE_PIPE) {
         pipe_samples<R, INTEG, PROF>(kp, c, item, local_block, acc, dump, lds);
     } else {
@@ -724,8 +736,9 @@ int launch_pdf_bins(const KBins& bins, const KProblem& kp, const double* d_dump,
 using LevelKernel = void (*)(const KArgs, ld_level_sums*, double*);
 
 template <typename R>
-LevelKernel pick_kernel(int integ, int profile, bool adaptive) {
-    if (adaptive) return level_kernel<R, KINTEG_SE_ADAPT, KPROFILE_NEUTRAL>;   // neutral only
+LevelKernel pick_kernel(int integ, int profile, bool adaptive, bool wide) {
+    if (adaptive)   // neutral profile only
+        return wide ? level_kernel<R, KINTEG_SE_ADAPT_WIDE, KPROFILE_NEUTRAL> : level_kernel<R, KINTEG_SE_ADAPT, KPROFILE_NEUTRAL>;
     switch (integ * 2 + profile) {
         case KINTEG_SE * 2 + KPROFILE_HOMOGENEOUS: return level_kernel<R, KINTEG_SE, KPROFILE_HOMOGENEOUS>;
         case KINTEG_SE * 2 + KPROFILE_NEUTRAL: return level_kernel<R, KINTEG_SE, KPROFILE_NEUTRAL>;
@@ -740,9 +753,15 @@ int launch_levels(const KArgs& args, uint32_t total_blocks, ld_level_sums* d_par
                   ld_level_sums* d_out, double* d_dump, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     if (total_blocks > 0) {
+        // adaptive steps: 64-bit tick counters if some item's T in ticks plus a coarse step
+        // (2^21 ticks) does not fit 32 bits
+        bool wide = false;
+        for (int i = 0; i < args.n_items; ++i)
+            wide |= (((uint64_t)args.prob.M0 << (args.items[i].level + kAdaptTickBits)) +
+                     ((uint64_t)2 << kAdaptTickBits)) >= ((uint64_t)1 << 32);
         const LevelKernel k = (args.precision == LD_FP32)
-                                  ? pick_kernel<float>(args.prob.integ, args.prob.profile, args.prob.adaptive)
-                                  : pick_kernel<double>(args.prob.integ, args.prob.profile, args.prob.adaptive);
+                                  ? pick_kernel<float>(args.prob.integ, args.prob.profile, args.prob.adaptive, wide)
+                                  : pick_kernel<double>(args.prob.integ, args.prob.profile, args.prob.adaptive, wide);
         hipLaunchKernelGGL(k, dim3(total_blocks), dim3(kBlock), 0, s, args, d_partials, d_dump);
         if (hipGetLastError() != hipSuccess) return LD_EDEVICE;
     }

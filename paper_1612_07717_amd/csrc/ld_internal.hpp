@@ -9,12 +9,14 @@
 namespace ldm {
 
 enum { KINTEG_SE = 0, KINTEG_GL = 1, KINTEG_BAOAB = 2,
-       KINTEG_SE_ADAPT = 3 };   // kernel variant: symplectic Euler with adaptive steps (Sec. 7)
+       KINTEG_SE_ADAPT = 3,       // kernel variants: symplectic Euler with adaptive steps (Sec. 7),
+       KINTEG_SE_ADAPT_WIDE = 4 };  // 32-bit tick counters, or 64-bit where T in ticks needs them
 enum { KPROFILE_HOMOGENEOUS = 0, KPROFILE_NEUTRAL = 1 };
 enum { KRELEASE_FIXED_W = 0, KRELEASE_GAUSSIAN_W = 1, KRELEASE_WELL_MIXED = 2 };
 enum { KQOI_MEAN_Z = 0, KQOI_P_ABOVE = 1, KQOI_P_BOX = 2, KQOI_VELOCITY = 3, KQOI_VELOCITY_SQ = 4 };
 
 constexpr int kFoldMax = 16;      // reflections allowed in one fold before a path is declared runaway
+constexpr int kAdaptTickBits = 20;    // adaptive steps: ticks of h_l / 2^20
 constexpr int kBlock = 256;       // threads per block of the level kernel (4 wave64)
 constexpr int kMaxItems = 40;     // (level, range) items per launch
 constexpr int kMaxCoef = 10;      // smoothing polynomial p_r, r <= 8
