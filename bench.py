@@ -353,6 +353,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--integrator", default="BAOAB", choices=["BAOAB", "GL"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plain-schedule", action="store_true",
+                    help="single_large: no early top-up (one launch per driver iteration)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy a 1 GiB buffer once (scale reference for HBM counters)")
     args = ap.parse_args()
@@ -435,7 +437,7 @@ def main():
     ws = torch.empty(ld.estimate_workspace_bytes(), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
     kw = dict(precision=args.precision, fixed_L=L, eps_is_relative=True, N_init=10000,
-              workspace=ws, stream=stream)
+              early_topup=not args.plain_schedule, workspace=ws, stream=stream)
 
     for _ in range(args.warmup):
         ld.estimate(eps, cfg, **kw)
@@ -483,6 +485,7 @@ def main():
                                f"{args.integrator}, z0 = 500 m, Gaussian w0, T = 1000 s, "
                                "dt_0 = T/8, levels 0..12, relative eps 1e-4, E[Z(T)]",
                    "paths": args.precision, "sums": "fp64 compensated",
+                   "schedule": "plain" if args.plain_schedule else "early top-up (short levels beside the long ones)",
                    "levels": L + 1, "N_l": last["N"], "fine_steps_per_step": last["fine_steps"],
                    "estimate_m": last["estimate"], "rmse_est_m": last["rmse_est"],
                    "time_to_eps_s": last["wall_seconds"], "kernel_s_per_step": dev_s / args.steps,

@@ -98,7 +98,7 @@ class EstimateOpts(C.Structure):
                 ("L_min", C.c_int32), ("L_max", C.c_int32), ("fixed_L", C.c_int32),
                 ("fixed_N", C.c_int32), ("eps_is_relative", C.c_int32), ("N_init", C.c_uint64),
                 ("alpha", C.c_double), ("precision", C.c_int32), ("stream_id", C.c_uint32),
-                ("seed", C.c_uint64), ("max_iter", C.c_int32), ("reserved", C.c_int32),
+                ("seed", C.c_uint64), ("max_iter", C.c_int32), ("early_topup", C.c_int32),
                 ("x_adapt", C.c_double), ("max_fine_steps", C.c_double),
                 ("d_workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
                 ("hip_stream", C.c_void_p)]
@@ -190,6 +190,16 @@ def load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                            "`python -m paper_1612_07717_amd.build`")
+    # PyTorch ships its own HIP runtime beside the system one this library links. One
+    # process can use both only if PyTorch's brings the device up first (the other order
+    # leaves PyTorch without a GPU), so it is initialised here, before the library can
+    # make its first HIP call; without a GPU this does nothing.
+    try:
+        import torch
+        if torch.cuda.is_available():
+            torch.cuda.init()
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     P, V = C.POINTER, C.c_void_p
     lib.mlmc_level_sums_workspace.argtypes = [C.c_uint64]
@@ -363,7 +373,7 @@ def level_samples(cfg, level, begin, n, precision="fp64", stream=None) -> np.nda
 
 def estimate_opts(cfg, *, precision="fp64", L_min=2, L_max=20, fixed_L=-1, fixed_N=False,
                   N_init=10000, eps_is_relative=False, alpha=1.0, max_iter=100,
-                  max_fine_steps=0.0, workspace=None, stream=None) -> EstimateOpts:
+                  max_fine_steps=0.0, early_topup=False, workspace=None, stream=None) -> EstimateOpts:
     o = EstimateOpts()
     load().mlmc_estimate_default_opts(C.byref(o))
     o.release = make_release(cfg)
@@ -378,6 +388,7 @@ def estimate_opts(cfg, *, precision="fp64", L_min=2, L_max=20, fixed_L=-1, fixed
     o.seed = int(cfg["seed"])
     o.max_iter = int(max_iter)
     o.max_fine_steps = float(max_fine_steps)
+    o.early_topup = int(bool(early_topup))
     o.x_adapt = float(cfg.get("x_adapt", 0.0))
     if workspace is not None:
         o.d_workspace = workspace.data_ptr()

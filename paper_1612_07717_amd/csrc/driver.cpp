@@ -91,6 +91,33 @@ void merge_into(HostSums& acc, const ld_level_sums& add) {
     acc.bad += add.n_nonfinite;
 }
 
+// Early top-up of the first iteration (ld_estimate_opts.early_topup). The levels are
+// split at L0 - kEarlyGap: the long ones (L0 - kEarlyGap < l <= L0) run their first
+// batch on the caller's stream, the short ones theirs on a second stream. As soon as the
+// short levels' sums are back, the variance rule is applied to them alone: with the sum
+// of sqrt(V_k C_k) over the short levels only, each N_l is at most what the full rule will
+// ask once the long levels are known (for an absolute eps). kEarlyFraction of it is drawn
+// at once, on the second stream, while the long levels still run; the ordinary
+// iterations follow. The draws are the same (sample indices from 0 upward on every
+// level), only their order in time changes, so the estimate is the plain MLMC estimate
+// of whatever N_l end up drawn.
+constexpr int32_t kEarlyGap = 5;
+constexpr double kEarlyFraction = 0.9;
+
+struct Batch {
+    ld_level_range r[LD_MAX_LEVELS];
+    int32_t n = 0;
+    void add(int32_t level, uint64_t begin, uint64_t count) {
+        if (count == 0) return;
+        r[n].level = level;
+        r[n].reserved = 0;
+        r[n].sample_begin = begin;
+        r[n].n_samples = count;
+        ++n;
+    }
+    size_t blocks() const { return n > 0 ? mlmc_level_sums_batch_workspace(r, n) / sizeof(ld_level_sums) : 0; }
+};
+
 }  // namespace
 
 // The decision of one iteration (shared by the scalar and the vector planners), given
@@ -259,7 +286,101 @@ int mlmc_estimate(double eps, const ld_qoi* qoi, ld_integrator integrator, const
     double device_s = 0.0;
     ld_level_sums host_batch[LD_MAX_LEVELS];
     rc = LD_OK;
+    if (opts.early_topup && !opts.fixed_N && L0 >= kEarlyGap) {
+        const int32_t Ls = L0 - kEarlyGap;               // short levels 0..Ls
+        Batch longb, shortb, topb;
+        for (int32_t l = Ls + 1; l <= L0; ++l) longb.add(l, 0, opts.N_init);
+        for (int32_t l = 0; l <= Ls; ++l) shortb.add(l, 0, opts.N_init);
+        const size_t slots = partial_bytes / sizeof(ld_level_sums);
+        const size_t off = longb.blocks();               // the second stream's partials follow
+        hipStream_t s2 = nullptr;
+        hipEvent_t e_long = nullptr, e_short = nullptr;
+        if (off + shortb.blocks() > slots || hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess) {
+            rc = fail(LD_EDEVICE, "early top-up: no second stream");
+        } else {
+            (void)hipEventCreate(&e_long);
+            (void)hipEventCreate(&e_short);
+            ld_level_sums* d_sums2 = d_sums + longb.n;
+            void* d_part2 = (void*)((ld_level_sums*)d_partials + off);
+            const size_t part2_bytes = partial_bytes - off * sizeof(ld_level_sums);
+            ld_level_sums h_long[LD_MAX_LEVELS], h_short[LD_MAX_LEVELS], h_top[LD_MAX_LEVELS];
+            if (timing) (void)hipEventRecord(ev0, stream);
+            rc = run_batch(&prob, integrator, opts.precision, longb.r, longb.n, d_sums, d_partials,
+                           partial_bytes, nullptr, stream);
+            if (rc == LD_OK && e_long) (void)hipEventRecord(e_long, stream);
+            if (rc == LD_OK)
+                rc = run_batch(&prob, integrator, opts.precision, shortb.r, shortb.n, d_sums2, d_part2,
+                               part2_bytes, nullptr, s2);
+            if (rc == LD_OK &&
+                (hipMemcpyAsync(h_short, d_sums2, shortb.n * sizeof(ld_level_sums), hipMemcpyDeviceToHost, s2) !=
+                     hipSuccess ||
+                 hipStreamSynchronize(s2) != hipSuccess))
+                rc = fail(LD_EDEVICE, "level sums failed (short levels)");
+            if (rc == LD_OK) {
+                for (int32_t j = 0; j < shortb.n; ++j) {
+                    merge_into(sums[shortb.r[j].level], h_short[j]);
+                    drawn[shortb.r[j].level] += shortb.r[j].n_samples;
+                }
+                // the variance rule over the short levels alone, no level added, no bias test
+                ld_plan_in ps = pin;
+                ps.L = Ls;
+                ps.fixed_L = Ls;
+                for (int32_t l = 0; l <= Ls; ++l) {
+                    ps.n[l] = sums[l].n;
+                    ps.sum1[l] = sums[l].s[0] + sums[l].c[0];
+                    ps.sum2[l] = sums[l].s[1] + sums[l].c[1];
+                }
+                ld_plan_out po;
+                mlmc_plan(&ps, &po);
+                uint64_t dn_s[LD_MAX_LEVELS] = {0};
+                for (int32_t l = 0; l <= Ls; ++l) {
+                    const double want = std::floor(kEarlyFraction * ((double)ps.n[l] + (double)po.dn[l]));
+                    dn_s[l] = (want > (double)ps.n[l]) ? (uint64_t)want - ps.n[l] : 0;
+                }
+                if (po.status == 0 && !exceeds_budget(opts.max_fine_steps, opts.M0, drawn, dn_s, Ls))
+                    for (int32_t l = 0; l <= Ls; ++l) topb.add(l, drawn[l], dn_s[l]);
+                if (topb.n > 0) {
+                    rc = run_batch(&prob, integrator, opts.precision, topb.r, topb.n, d_sums2, d_part2,
+                                   part2_bytes, nullptr, s2);
+                    if (rc == LD_OK &&
+                        (hipMemcpyAsync(h_top, d_sums2, topb.n * sizeof(ld_level_sums), hipMemcpyDeviceToHost,
+                                        s2) != hipSuccess ||
+                         hipStreamSynchronize(s2) != hipSuccess))
+                        rc = fail(LD_EDEVICE, "level sums failed (early top-up)");
+                }
+                if (rc == LD_OK && e_short) (void)hipEventRecord(e_short, s2);
+            }
+            if (rc == LD_OK &&
+                (hipMemcpyAsync(h_long, d_sums, longb.n * sizeof(ld_level_sums), hipMemcpyDeviceToHost, stream) !=
+                     hipSuccess ||
+                 hipStreamSynchronize(stream) != hipSuccess || hipStreamSynchronize(s2) != hipSuccess))
+                rc = fail(LD_EDEVICE, "level sums failed (long levels)");
+            if (rc == LD_OK) {
+                for (int32_t j = 0; j < longb.n; ++j) {
+                    merge_into(sums[longb.r[j].level], h_long[j]);
+                    drawn[longb.r[j].level] += longb.r[j].n_samples;
+                }
+                for (int32_t j = 0; j < topb.n; ++j) {
+                    merge_into(sums[topb.r[j].level], h_top[j]);
+                    drawn[topb.r[j].level] += topb.r[j].n_samples;
+                }
+                out->launches += topb.n > 0 ? 3 : 2;
+                if (timing) {   // the overlapped span: from the first launch to the later end
+                    float a = 0.f, b = 0.f;
+                    if (hipEventElapsedTime(&a, ev0, e_long) == hipSuccess) {
+                        if (e_short && hipEventElapsedTime(&b, ev0, e_short) != hipSuccess) b = 0.f;
+                        device_s += std::max(a, b) * 1e-3;
+                    }
+                }
+                std::memset(dn, 0, sizeof dn);               // the loop below starts by planning
+            }
+        }
+        if (e_long) (void)hipEventDestroy(e_long);
+        if (e_short) (void)hipEventDestroy(e_short);
+        if (s2) (void)hipStreamDestroy(s2);
+    }
     for (;;) {
+        if (rc != LD_OK) break;
         ld_level_range ranges[LD_MAX_LEVELS];
         int32_t nr = 0;
         for (int32_t l = 0; l <= pin.L; ++l) {

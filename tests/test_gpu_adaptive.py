@@ -6,7 +6,10 @@
 - FP32 paths (step rule in FP32) agree with FP64 to rounding on level 0 and in law on
   coupled levels, where a tick of difference can re-pair the draws of a sample;
 - the FP64 adaptive estimate takes the oracle driver's decisions;
-- with the reference height at the cut-off the kernel reproduces uniform SE.
+- with the reference height at the cut-off the kernel reproduces uniform SE;
+- several samples per wave (the per-wave hand-out), the 64-bit tick kernel, homogeneous
+  turbulence (runs the uniform kernel) and the binned concentration path all match the
+  oracle.
 """
 import sys
 
@@ -117,3 +120,25 @@ def test_homogeneous_turbulence_never_adapts():
         got = ld.level_samples(cfg, level, 0, 1000, "fp64")
         ref = oracle.level_samples(cfg, level, 0, 1000)
         assert _rel(got, ref).max() <= 1e-12
+
+
+def test_level_with_64_bit_ticks_matches_oracle():
+    """M_7 = 40 * 2^7 = 5120 steps: T in ticks (5120 * 2^20) needs 64-bit counters, the
+    other adaptive kernel; FP64 samples equal the oracle's."""
+    cfg = W.problem(integrator="SE", M0=40, x_adapt=50.0)
+    say("adaptive SE level 7 n=96 (64-bit ticks)")
+    got = ld.level_samples(cfg, 7, 17, 96, "fp64")
+    ref = oracle.level_samples(cfg, 7, 17, 96)
+    assert _rel(got, ref).max() <= 1e-12
+
+
+def test_binned_concentration_with_adaptive_steps_matches_oracle():
+    """The p.d.f. path (dump of the level kernel, then the bins kernel) with adaptive
+    steps: per-bin FP64 sums equal the oracle's."""
+    cfg = W.problem(integrator="SE", M0=40, x_adapt=50.0, r=4, delta=100.0)
+    g = ld.pdf_level_sums(cfg, 2, 3, 1500, 0.0, 50.0, 20, precision="fp64")
+    o = oracle.pdf_level_sums(cfg, 2, 3, 1500, 0.0, 50.0, 20)
+    for i, (x, y) in enumerate(zip(g, o)):
+        assert x["n"] == y["n"] and x["n_nonfinite"] == y["n_nonfinite"], i
+        for key in ("sum_y", "sum_y2", "sum_pf", "sum_pf2"):
+            assert abs(x[key] - y[key]) <= 1e-12 * max(abs(x[key]), abs(y[key])) + 1e-12, (i, key)

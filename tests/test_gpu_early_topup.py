@@ -1,0 +1,64 @@
+"""GPU tests of the early top-up schedule of mlmc_estimate (ld_estimate_opts.early_topup).
+
+The short levels' first batch runs beside the long levels' on a second stream and part of
+their top-up is drawn before the long levels end. The draws are the same as in the plain
+schedule (indices from 0 on every level), so:
+- the FP64 estimate equals the oracle's MLMC estimate over the same N_l (sums over
+  [0, N_l) on every level, recomputed on the CPU) within 1e-11;
+- the run is deterministic (two calls agree bit for bit);
+- it converges like the plain schedule, to an estimate within the statistical error, and
+  draws at least 0.9 of the plain schedule's samples on the short levels;
+- too few levels (L0 < 5) and fixed_N fall back to the plain schedule exactly.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import paper_1612_07717_amd as ld
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+CFG = W.single_large("BAOAB")
+KW = dict(fixed_L=7, eps_is_relative=True, N_init=2000)
+
+
+def test_fp64_estimate_equals_oracle_over_the_same_samples():
+    say("early top-up FP64, levels 0..7, eps_rel 1e-3")
+    g = ld.estimate(1e-3, CFG, precision="fp64", early_topup=True, **KW)
+    assert g["status"] == 1 and g["launches"] >= 3
+    est = 0.0
+    for l, n in enumerate(g["N"]):
+        s = oracle.level_sums(CFG, l, 0, n)
+        est += s["sum_y"] / s["n"]
+    say(f"  N={g['N']} estimate {g['estimate']:.9f} oracle {est:.9f}")
+    assert abs(g["estimate"] - est) <= 1e-11 * abs(est)
+
+
+def test_deterministic_and_consistent_with_the_plain_schedule():
+    a = ld.estimate(1e-3, CFG, precision="fp32", early_topup=True, **KW)
+    b = ld.estimate(1e-3, CFG, precision="fp32", early_topup=True, **KW)
+    assert a["N"] == b["N"] and a["estimate"] == b["estimate"]
+    p = ld.estimate(1e-3, CFG, precision="fp32", **KW)
+    say(f"  early N={a['N']} plain N={p['N']}")
+    assert a["status"] == p["status"] == 1
+    assert a["rmse_est"] <= 1e-3 * abs(a["estimate"]) * 1.01
+    assert abs(a["estimate"] - p["estimate"]) <= 3.0 * np.sqrt(a["stat_var"] + p["stat_var"])
+    for l in range(3):                      # short levels 0..L0-5
+        assert a["N"][l] >= 0.9 * p["N"][l] - 1
+
+
+def test_falls_back_to_the_plain_schedule():
+    for kw in (dict(fixed_L=4, eps_is_relative=True, N_init=2000),
+               dict(fixed_L=7, fixed_N=True, eps_is_relative=True, N_init=500)):
+        a = ld.estimate(1e-3, CFG, precision="fp64", early_topup=True, **kw)
+        b = ld.estimate(1e-3, CFG, precision="fp64", **kw)
+        assert a["N"] == b["N"] and a["estimate"] == b["estimate"]
