@@ -246,7 +246,8 @@ typedef struct {
     double fine_steps;       /* sum_l N_l M_l: coupled particle-steps */
     double integrator_steps; /* sum_l N_l (M_l + M_l/2) (M_0 on level 0) */
     double wall_seconds;
-    double device_seconds;   /* time inside the level-sum kernels (HIP events) */
+    double device_seconds;   /* time inside the level-sum kernels (HIP events), summed over
+                                streams where batches run side by side */
     int32_t launches;
     int32_t reserved2;
 } ld_estimate_result;

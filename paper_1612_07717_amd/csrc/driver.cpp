@@ -294,11 +294,12 @@ int mlmc_estimate(double eps, const ld_qoi* qoi, ld_integrator integrator, const
         const size_t slots = partial_bytes / sizeof(ld_level_sums);
         const size_t off = longb.blocks();               // the second stream's partials follow
         hipStream_t s2 = nullptr;
-        hipEvent_t e_long = nullptr, e_short = nullptr;
+        hipEvent_t e_long = nullptr, e_short0 = nullptr, e_short = nullptr;
         if (off + shortb.blocks() > slots || hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess) {
             rc = fail(LD_EDEVICE, "early top-up: no second stream");
         } else {
             (void)hipEventCreate(&e_long);
+            (void)hipEventCreate(&e_short0);
             (void)hipEventCreate(&e_short);
             ld_level_sums* d_sums2 = d_sums + longb.n;
             void* d_part2 = (void*)((ld_level_sums*)d_partials + off);
@@ -308,14 +309,24 @@ int mlmc_estimate(double eps, const ld_qoi* qoi, ld_integrator integrator, const
             rc = run_batch(&prob, integrator, opts.precision, longb.r, longb.n, d_sums, d_partials,
                            partial_bytes, nullptr, stream);
             if (rc == LD_OK && e_long) (void)hipEventRecord(e_long, stream);
+            // kernel time of the second stream: each of its batches between two events
+            double s2_seconds = 0.0;
+            auto s2_span = [&]() {
+                float ms = 0.f;
+                if (e_short0 && e_short && hipEventElapsedTime(&ms, e_short0, e_short) == hipSuccess)
+                    s2_seconds += ms * 1e-3;
+            };
+            if (rc == LD_OK && e_short0) (void)hipEventRecord(e_short0, s2);
             if (rc == LD_OK)
                 rc = run_batch(&prob, integrator, opts.precision, shortb.r, shortb.n, d_sums2, d_part2,
                                part2_bytes, nullptr, s2);
+            if (rc == LD_OK && e_short) (void)hipEventRecord(e_short, s2);
             if (rc == LD_OK &&
                 (hipMemcpyAsync(h_short, d_sums2, shortb.n * sizeof(ld_level_sums), hipMemcpyDeviceToHost, s2) !=
                      hipSuccess ||
                  hipStreamSynchronize(s2) != hipSuccess))
                 rc = fail(LD_EDEVICE, "level sums failed (short levels)");
+            if (rc == LD_OK) s2_span();
             if (rc == LD_OK) {
                 for (int32_t j = 0; j < shortb.n; ++j) {
                     merge_into(sums[shortb.r[j].level], h_short[j]);
@@ -340,15 +351,17 @@ int mlmc_estimate(double eps, const ld_qoi* qoi, ld_integrator integrator, const
                 if (po.status == 0 && !exceeds_budget(opts.max_fine_steps, opts.M0, drawn, dn_s, Ls))
                     for (int32_t l = 0; l <= Ls; ++l) topb.add(l, drawn[l], dn_s[l]);
                 if (topb.n > 0) {
+                    if (e_short0) (void)hipEventRecord(e_short0, s2);
                     rc = run_batch(&prob, integrator, opts.precision, topb.r, topb.n, d_sums2, d_part2,
                                    part2_bytes, nullptr, s2);
+                    if (rc == LD_OK && e_short) (void)hipEventRecord(e_short, s2);
                     if (rc == LD_OK &&
                         (hipMemcpyAsync(h_top, d_sums2, topb.n * sizeof(ld_level_sums), hipMemcpyDeviceToHost,
                                         s2) != hipSuccess ||
                          hipStreamSynchronize(s2) != hipSuccess))
                         rc = fail(LD_EDEVICE, "level sums failed (early top-up)");
+                    if (rc == LD_OK) s2_span();
                 }
-                if (rc == LD_OK && e_short) (void)hipEventRecord(e_short, s2);
             }
             if (rc == LD_OK &&
                 (hipMemcpyAsync(h_long, d_sums, longb.n * sizeof(ld_level_sums), hipMemcpyDeviceToHost, stream) !=
@@ -365,17 +378,16 @@ int mlmc_estimate(double eps, const ld_qoi* qoi, ld_integrator integrator, const
                     drawn[topb.r[j].level] += topb.r[j].n_samples;
                 }
                 out->launches += topb.n > 0 ? 3 : 2;
-                if (timing) {   // the overlapped span: from the first launch to the later end
-                    float a = 0.f, b = 0.f;
-                    if (hipEventElapsedTime(&a, ev0, e_long) == hipSuccess) {
-                        if (e_short && hipEventElapsedTime(&b, ev0, e_short) != hipSuccess) b = 0.f;
-                        device_s += std::max(a, b) * 1e-3;
-                    }
+                if (timing) {   // kernel time of both streams, summed as for one stream
+                    float a = 0.f;
+                    if (hipEventElapsedTime(&a, ev0, e_long) == hipSuccess) device_s += a * 1e-3;
+                    device_s += s2_seconds;
                 }
                 std::memset(dn, 0, sizeof dn);               // the loop below starts by planning
             }
         }
         if (e_long) (void)hipEventDestroy(e_long);
+        if (e_short0) (void)hipEventDestroy(e_short0);
         if (e_short) (void)hipEventDestroy(e_short);
         if (s2) (void)hipStreamDestroy(s2);
     }
