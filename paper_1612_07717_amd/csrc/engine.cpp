@@ -4,7 +4,8 @@
 // (LD_MAX_LEVELS ld_level_sums) live in device memory for the query's lifetime. An
 // iteration gathers every query's planned (level, range) pairs, cuts them into tiles
 // with a rule that depends on the range alone, uploads the tile and range tables, and
-// replays a captured graph: reset queue counters -> persistent kernel per profile ->
+// replays a captured graph: reset queue counters -> persistent kernel per queue (profile
+// kind, or adaptive symplectic Euler) ->
 // merge of each range's partials into the running sums. The running sums of the
 // touched slots come back and each query's planner (mlmc_plan, Sec. 3.3 / Sec. 6)
 // decides its next samples; converged queries leave, new ones are admitted between
@@ -72,7 +73,7 @@ struct ld_engine {
     KRange* h_ranges = nullptr;
     KTile* h_tiles = nullptr;
     ld_level_sums* h_running = nullptr;
-    hipGraphExec_t graph[4] = {nullptr, nullptr, nullptr, nullptr};   // by profile mask
+    hipGraphExec_t graph[1 << kNumQueues] = {};   // by queue mask
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::vector<Query> q;        // by slot
     int64_t next_handle = 0;
@@ -95,8 +96,8 @@ int validate_query(const ld_query* qq) {
         return fail(LD_EINVAL, "need 0 <= L_min <= L_max < LD_MAX_LEVELS");
     if (qq->N_init < 2) return fail(LD_EINVAL, "N_init must be >= 2");
     if (!(qq->max_fine_steps >= 0.0)) return fail(LD_EINVAL, "max_fine_steps must be >= 0");
-    if (qq->problem.x_adapt > 0.0)
-        return fail(LD_EINVAL, "adaptive steps run through mlmc_estimate, not the engine");
+    if (qq->problem.x_adapt > 0.0 && std::ldexp((double)qq->problem.M0, qq->L_max) > 67108864.0)
+        return fail(LD_EINVAL, "adaptive steps need M0 * 2^L_max <= 2^26");
     if (std::ldexp((double)qq->problem.M0, qq->L_max) > 2147483648.0)
         return fail(LD_EINVAL, "M0 * 2^L_max must not exceed 2^31");
     return check_stability(&qq->problem, qq->integrator, 0);
@@ -117,6 +118,21 @@ void release_resources(ld_engine* e) {
     if (e->h_tiles) (void)hipHostFree(e->h_tiles);
     if (e->h_running) (void)hipHostFree(e->h_running);
     if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
+}
+
+// STREAM tiles of a range: 256 lanes x spl samples each. Adaptive symplectic Euler takes
+// the level kernel's plan for its precision (one resident round of blocks), so its tiles
+// are that kernel's blocks and a query's sums are the same bit for bit.
+void stream_tiles(const ld_engine* e, const Query& qu, uint64_t n, uint32_t* spl, uint32_t* nb) {
+    if (qu.kp.adaptive) {
+        plan_item(n, spl, nb, e->opts.precision == LD_FP32 ? kAdaptiveTargetBlocksFp32 : kAdaptiveTargetBlocksFp64);
+        return;
+    }
+    const uint64_t per = (uint64_t)kBlock;
+    const uint64_t T = std::max<uint64_t>(1, e->opts.target_tiles);
+    const uint64_t s = (n > per * T) ? (n + per * T - 1) / (per * T) : 1;
+    *spl = (uint32_t)s;
+    *nb = (uint32_t)((n + per * s - 1) / (per * s));
 }
 
 // Tiles of one range; the rule depends on the range alone.
@@ -140,12 +156,10 @@ void tile_range(const ld_engine* e, uint32_t slot, const Query& qu, int32_t leve
         }
         return;
     }
-    const uint64_t per = (uint64_t)kBlock;
-    const uint64_t T = std::max<uint64_t>(1, e->opts.target_tiles);
-    const uint64_t spl = (n > per * T) ? (n + per * T - 1) / (per * T) : 1;
-    const uint64_t nb = (n + per * spl - 1) / (per * spl);
+    uint32_t spl = 1, nb = 0;
+    stream_tiles(e, qu, n, &spl, &nb);
     t.mode = KMODE_STREAM;
-    t.spl = (uint32_t)spl;
+    t.spl = spl;
     for (uint64_t b = 0; b < nb; ++b) {
         t.local_block = (uint32_t)b;
         out.push_back(t);
@@ -156,10 +170,9 @@ uint64_t tiles_of_range(const ld_engine* e, const Query& qu, int32_t level, uint
     const uint64_t M = (uint64_t)qu.prob.M0 << level;
     if (level >= 1 && n <= e->opts.pipe_max_samples && M >= e->opts.pipe_min_steps && !qu.kp.adaptive)
         return (n + 63) / 64;
-    const uint64_t per = (uint64_t)kBlock;
-    const uint64_t T = std::max<uint64_t>(1, e->opts.target_tiles);
-    const uint64_t spl = (n > per * T) ? (n + per * T - 1) / (per * T) : 1;
-    return (n + per * spl - 1) / (per * spl);
+    uint32_t spl = 1, nb = 0;
+    stream_tiles(e, qu, n, &spl, &nb);
+    return nb;
 }
 
 // One graph per set of profiles present (the persistent kernel of a profile without
@@ -372,46 +385,49 @@ int ld_engine_step(ld_engine* e, int32_t* n_active) {
     std::stable_sort(pend.begin(), pend.end(),
                      [&](const Pending& a, const Pending& b) { return steps_of(a) > steps_of(b); });
     const double top = steps_of(pend.front());
-    // 2. tiles, grouped by profile; ranges that do not fit wait for the next iteration
-    std::vector<KTile> tiles[2];
-    std::vector<KRange> ranges[2];
-    std::vector<Pending> taken[2];
+    // 2. tiles, grouped by queue (profile kind, or adaptive SE); ranges that do not fit
+    //    wait for the next iteration
+    std::vector<KTile> tiles[kNumQueues];
+    std::vector<KRange> ranges[kNumQueues];
+    std::vector<Pending> taken[kNumQueues];
     uint64_t total = 0;
     for (const Pending& p : pend) {
         const Query& qu = e->q[p.slot];
         const uint64_t nt = tiles_of_range(e, qu, p.level, p.n);
-        if (total + nt > e->max_tiles || ranges[0].size() + ranges[1].size() >= e->max_ranges) continue;
-        const int prof = qu.kp.profile;
+        size_t n_ranges = 0;
+        for (const auto& v : ranges) n_ranges += v.size();
+        if (total + nt > e->max_tiles || n_ranges >= e->max_ranges) continue;
+        const int qi = qu.kp.adaptive ? (int)KQUEUE_ADAPT : qu.kp.profile;
         const uint16_t prio = (uint16_t)std::max(0, 3 - (int)std::lround(std::log2(top / steps_of(p))));
         KRange r;
         r.slot = (uint32_t)p.slot;
         r.level = p.level;
-        r.tile_begin = (uint32_t)tiles[prof].size();
-        tile_range(e, (uint32_t)p.slot, qu, p.level, p.begin, p.n, prio, tiles[prof]);
-        r.n_tiles = (uint32_t)(tiles[prof].size() - r.tile_begin);
-        ranges[prof].push_back(r);
-        taken[prof].push_back(p);
+        r.tile_begin = (uint32_t)tiles[qi].size();
+        tile_range(e, (uint32_t)p.slot, qu, p.level, p.begin, p.n, prio, tiles[qi]);
+        r.n_tiles = (uint32_t)(tiles[qi].size() - r.tile_begin);
+        ranges[qi].push_back(r);
+        taken[qi].push_back(p);
         total += nt;
     }
     if (total == 0) return fail(LD_ENOMEM, "a single range exceeds the engine's tile budget");
-    // concatenate: profile 1 (neutral) tiles first, then profile 0
-    const uint32_t n1 = (uint32_t)tiles[1].size(), n0 = (uint32_t)tiles[0].size();
+    // concatenate the queues: neutral, homogeneous, adaptive
+    const int order[kNumQueues] = {KPROFILE_NEUTRAL, KPROFILE_HOMOGENEOUS, KQUEUE_ADAPT};
     std::vector<KTile> all;
-    all.reserve(n1 + n0);
-    all.insert(all.end(), tiles[1].begin(), tiles[1].end());
-    all.insert(all.end(), tiles[0].begin(), tiles[0].end());
     std::vector<KRange> rall;
     std::vector<Pending> pall;
-    for (KRange r : ranges[1]) rall.push_back(r);
-    for (KRange r : ranges[0]) {
-        r.tile_begin += n1;
-        rall.push_back(r);
-    }
-    pall.insert(pall.end(), taken[1].begin(), taken[1].end());
-    pall.insert(pall.end(), taken[0].begin(), taken[0].end());
     std::memset(e->h_hdr, 0, sizeof(KHeader));
-    e->h_hdr->queue[KPROFILE_NEUTRAL] = KQueue{0, n1, 0, 0};
-    e->h_hdr->queue[KPROFILE_HOMOGENEOUS] = KQueue{n1, n0, 1, 0};
+    uint32_t mask = 0;
+    for (int qi : order) {
+        const uint32_t first = (uint32_t)all.size(), n = (uint32_t)tiles[qi].size();
+        all.insert(all.end(), tiles[qi].begin(), tiles[qi].end());
+        for (KRange r : ranges[qi]) {
+            r.tile_begin += first;
+            rall.push_back(r);
+        }
+        pall.insert(pall.end(), taken[qi].begin(), taken[qi].end());
+        e->h_hdr->queue[qi] = KQueue{first, n, (uint32_t)qi, 0};
+        if (n > 0) mask |= 1u << qi;
+    }
     e->h_hdr->n_ranges = (uint32_t)rall.size();
     std::memcpy(e->h_ranges, rall.data(), rall.size() * sizeof(KRange));
     // 3. upload, run, read back
@@ -421,7 +437,6 @@ int ld_engine_step(ld_engine* e, int32_t* n_active) {
         hipMemcpyAsync(e->d_tiles, all.data(), all.size() * sizeof(KTile), hipMemcpyHostToDevice, e->stream) !=
             hipSuccess)
         return fail(LD_EDEVICE, "uploading the tile tables failed");
-    const uint32_t mask = (n1 > 0 ? 1u << KPROFILE_NEUTRAL : 0u) | (n0 > 0 ? 1u << KPROFILE_HOMOGENEOUS : 0u);
     if (e->opts.use_graph && e->graph[mask] == nullptr) {
         int rc = capture_graph(e, mask);
         if (rc != LD_OK) return rc;

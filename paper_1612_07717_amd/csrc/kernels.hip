@@ -522,8 +522,10 @@ __global__ __launch_bounds__(kBlock, 3) void level_kernel(const KArgs args,
 // (query, level, range)) from a queue until it is empty; each tile writes its own
 // partial, so the result does not depend on which block ran which tile. Integrators
 // are chosen per tile (uniform per block); the profile is a template parameter.
+// ADAPT: the queue of adaptive symplectic Euler tiles (neutral profile), each run as the
+// level kernel runs that block, with 32- or 64-bit tick counters as its level needs.
 // ---------------------------------------------------------------------------------
-template <typename R, int PROF>
+template <typename R, int PROF, bool ADAPT = false>
 __global__ __launch_bounds__(kBlock) void persistent_kernel(const KHeader* __restrict__ hdr,
                                                             const KTile* __restrict__ tiles,
                                                             const KProblem* __restrict__ problems,
@@ -531,7 +533,7 @@ __global__ __launch_bounds__(kBlock) void persistent_kernel(const KHeader* __res
                                                             uint32_t* __restrict__ counters) {
     __shared__ uint32_t sh_tile;
     __shared__ PipeLds<R> lds;
-    const KQueue q = hdr->queue[PROF];
+    const KQueue q = hdr->queue[ADAPT ? (int)KQUEUE_ADAPT : PROF];
     const uint32_t wave = wave_index();
     const uint32_t lane = threadIdx.x & 63u;
     // The loop boundary holds no single-lane region (a divergent region there can be
@@ -562,10 +564,18 @@ __global__ __launch_bounds__(kBlock) void persistent_kernel(const KHeader* __res
         set_priority(tile.prio);
         Acc acc;
         acc_zero(acc);
-        switch (kp.integ) {
-            case KINTEG_SE: run_block<R, KINTEG_SE, PROF>(kp, item, tile.local_block, acc, nullptr, lds); break;
-            case KINTEG_GL: run_block<R, KINTEG_GL, PROF>(kp, item, tile.local_block, acc, nullptr, lds); break;
-            default: run_block<R, KINTEG_BAOAB, PROF>(kp, item, tile.local_block, acc, nullptr, lds); break;
+        if constexpr (ADAPT) {
+            if (((uint64_t)kp.M0 << (tile.level + kAdaptTickBits)) + ((uint64_t)2 << kAdaptTickBits) <
+                ((uint64_t)1 << 32))
+                run_block<R, KINTEG_SE_ADAPT, PROF>(kp, item, tile.local_block, acc, nullptr, lds);
+            else
+                run_block<R, KINTEG_SE_ADAPT_WIDE, PROF>(kp, item, tile.local_block, acc, nullptr, lds);
+        } else {
+            switch (kp.integ) {
+                case KINTEG_SE: run_block<R, KINTEG_SE, PROF>(kp, item, tile.local_block, acc, nullptr, lds); break;
+                case KINTEG_GL: run_block<R, KINTEG_GL, PROF>(kp, item, tile.local_block, acc, nullptr, lds); break;
+                default: run_block<R, KINTEG_BAOAB, PROF>(kp, item, tile.local_block, acc, nullptr, lds); break;
+            }
         }
         block_reduce_all(acc);
         if (wave == 0) store_sums(&partials[q.first + t], acc);   // same values from every lane
@@ -770,15 +780,16 @@ int launch_levels(const KArgs& args, uint32_t total_blocks, ld_level_sums* d_par
     return LD_OK;
 }
 
-int launch_engine_iteration(int precision, uint32_t grid_blocks, uint32_t profile_mask,
+int launch_engine_iteration(int precision, uint32_t grid_blocks, uint32_t queue_mask,
                             const KHeader* d_hdr, const KTile* d_tiles, const KProblem* d_problems,
                             ld_level_sums* d_partials, uint32_t* d_counters,
                             const KRange* d_ranges, ld_level_sums* d_running,
                             ld_level_sums* d_range_out, void* stream) {
     hipStream_t s = (hipStream_t)stream;
-    const bool neutral = (profile_mask >> KPROFILE_NEUTRAL) & 1u;
-    const bool homogeneous = (profile_mask >> KPROFILE_HOMOGENEOUS) & 1u;
-    hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, d_counters, 2);
+    const bool neutral = (queue_mask >> KPROFILE_NEUTRAL) & 1u;
+    const bool homogeneous = (queue_mask >> KPROFILE_HOMOGENEOUS) & 1u;
+    const bool adapt = (queue_mask >> KQUEUE_ADAPT) & 1u;
+    hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, d_counters, (int)kNumQueues);
     if (precision == LD_FP32) {
         if (neutral)
             hipLaunchKernelGGL((persistent_kernel<float, KPROFILE_NEUTRAL>), dim3(grid_blocks), dim3(kBlock), 0,
@@ -786,6 +797,9 @@ int launch_engine_iteration(int precision, uint32_t grid_blocks, uint32_t profil
         if (homogeneous)
             hipLaunchKernelGGL((persistent_kernel<float, KPROFILE_HOMOGENEOUS>), dim3(grid_blocks), dim3(kBlock),
                                0, s, d_hdr, d_tiles, d_problems, d_partials, d_counters);
+        if (adapt)
+            hipLaunchKernelGGL((persistent_kernel<float, KPROFILE_NEUTRAL, true>), dim3(grid_blocks),
+                               dim3(kBlock), 0, s, d_hdr, d_tiles, d_problems, d_partials, d_counters);
     } else {
         if (neutral)
             hipLaunchKernelGGL((persistent_kernel<double, KPROFILE_NEUTRAL>), dim3(grid_blocks), dim3(kBlock), 0,
@@ -793,6 +807,9 @@ int launch_engine_iteration(int precision, uint32_t grid_blocks, uint32_t profil
         if (homogeneous)
             hipLaunchKernelGGL((persistent_kernel<double, KPROFILE_HOMOGENEOUS>), dim3(grid_blocks), dim3(kBlock),
                                0, s, d_hdr, d_tiles, d_problems, d_partials, d_counters);
+        if (adapt)
+            hipLaunchKernelGGL((persistent_kernel<double, KPROFILE_NEUTRAL, true>), dim3(grid_blocks),
+                               dim3(kBlock), 0, s, d_hdr, d_tiles, d_problems, d_partials, d_counters);
     }
     hipLaunchKernelGGL(merge_ranges_kernel, dim3(kMergeGrid), dim3(kBlock), 0, s, d_hdr, d_ranges, d_partials,
                        d_running, d_range_out);

@@ -92,8 +92,12 @@ struct KQueue {
     uint32_t pad;
 };
 
+// Tile queues of an engine iteration: one per profile kind, and one for adaptive
+// symplectic Euler (neutral profile), whose tiles run in a kernel of their own.
+enum { KQUEUE_ADAPT = 2, kNumQueues = 3 };
+
 struct KHeader {
-    KQueue queue[2];        // by profile kind
+    KQueue queue[kNumQueues];   // [KPROFILE_*], [KQUEUE_ADAPT]
     uint32_t n_ranges;
     uint32_t pad[3];
 };
@@ -109,9 +113,9 @@ struct KRange {
 constexpr int kMergeGrid = 256;   // blocks of the range-merge kernel (grid-stride)
 
 // Enqueues one engine iteration: reset the queue counters, the persistent kernel of
-// each profile whose bit (1 << KPROFILE_*) is set in profile_mask, then the range
-// merge into the running sums.
-int launch_engine_iteration(int precision, uint32_t grid_blocks, uint32_t profile_mask,
+// each queue whose bit (1 << KPROFILE_*, 1 << KQUEUE_ADAPT) is set in queue_mask, then
+// the range merge into the running sums.
+int launch_engine_iteration(int precision, uint32_t grid_blocks, uint32_t queue_mask,
                             const KHeader* d_hdr, const KTile* d_tiles, const KProblem* d_problems,
                             ld_level_sums* d_partials, uint32_t* d_counters,
                             const KRange* d_ranges, ld_level_sums* d_running,

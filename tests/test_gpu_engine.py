@@ -130,3 +130,22 @@ def test_mixed_profiles_batch_equals_single():
         say(f"{c['profile']} {c['integrator']}: {m['estimate']:.6f} N={m['N']}")
         assert m["N"] == s["N"] and m["estimate"] == s["estimate"]
     assert homog[0]["estimate"] == mixed[0]["estimate"] and homog[1]["estimate"] == mixed[2]["estimate"]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_adaptive_queries_equal_single_estimates(prec):
+    """Adaptive symplectic Euler queries (Sec. 7) run in the engine's third queue, mixed
+    with uniform queries of both profiles; each equals its mlmc_estimate bit for bit."""
+    base = W.problem(integrator="SE", M0=40)
+    cfgs = [(dict(base, x_adapt=50.0), 5e-3, True),
+            (dict(base, x_adapt=50.0, z0=120.0, seed=9), 1e-2, True),
+            (W.neutral(300.0, "BAOAB"), 5e-3, True),
+            (W.homogeneous(x_adapt=50.0), 1e-2, True)]
+    qs = [_query(c, e, rel, N_init=2000, L_max=8) for c, e, rel in cfgs]
+    batch = ld.estimate_batch(qs, precision=prec)
+    for (c, e, rel), b in zip(cfgs, batch):
+        s = ld.estimate(e, c, precision=prec, eps_is_relative=rel, N_init=2000, L_max=8)
+        say(f"engine {prec} {c['integrator']} x_adapt={c.get('x_adapt', 0)}: {b['estimate']:.6f} N={b['N']}")
+        assert b["N"] == s["N"] and b["L"] == s["L"]
+        assert b["estimate"] == s["estimate"]
+        assert b["status"] == s["status"] == 1

@@ -137,3 +137,17 @@ def test_cost_budget_stops_engine_and_driver_alike():
         assert r["status"] == 2 and r["N"] == d["N"] and r["estimate"] == d["estimate"]
     free = ld.estimate(1e-4, c, precision="fp32", eps_is_relative=True, N_init=2000)
     assert free["fine_steps"] > budget and free["status"] == 1
+
+
+@pytest.mark.parametrize("policy", ["batch", "fifo"])
+def test_adaptive_queries_are_served(policy):
+    """Adaptive symplectic Euler queries (Sec. 7) served beside uniform ones: each result
+    equals mlmc_estimate's on the same query."""
+    base = W.problem(integrator="SE", M0=40)
+    cfgs = [dict(base, x_adapt=50.0), W.neutral(400.0, "GL"), dict(base, x_adapt=50.0, z0=90.0, seed=4)]
+    with ld.Server(policy=policy, precision="fp32") as srv:
+        tickets = [srv.submit(ld.make_query(c, 1e-2, N_init=2000, L_max=8)) for c in cfgs]
+        got = [srv.wait(t, timeout=120.0)[0] for t in tickets]
+    for c, r in zip(cfgs, got):
+        e = ld.estimate(1e-2, c, precision="fp32", eps_is_relative=True, N_init=2000, L_max=8)
+        assert r["N"] == e["N"] and r["estimate"] == e["estimate"]

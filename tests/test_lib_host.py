@@ -267,7 +267,7 @@ def test_pdf_arguments_rejected_without_device(lib):
 def test_adaptive_steps_validation_and_stability(lib):
     """x_adapt > 0 selects the adaptive symplectic Euler of Sec. 7: SE only, the
     stability condition uses lambda(x_adapt) (dt_0 = T/8 becomes stable with x_adapt =
-    50 m), and the engine leaves such queries to mlmc_estimate."""
+    50 m); the engine takes adaptive queries under the same limits."""
     se8 = W.single_large("SE")                                   # M0 = 8: lambda_max h_0 = 6.45
     assert _call_level_sums(lib, se8, level=0) == ld.LD_EUNSTABLE
     ada = dict(se8, x_adapt=50.0)                                # lambda(50 m) h_0 = 1.25
@@ -277,6 +277,8 @@ def test_adaptive_steps_validation_and_stability(lib):
     assert _call_level_sums(lib, dict(ada, x_adapt=2000.0), level=0) == ld.LD_EINVAL
     assert _call_level_sums(lib, dict(ada, x_adapt=900.0), level=0) == ld.LD_EINVAL   # > 64x shorter steps
     assert _call_level_sums(lib, dict(ada, M0=1 << 20), level=7) == ld.LD_EINVAL      # M > 2^26
-    q = ld.make_query(ada, 1e-2)
+    q = ld.make_query(ada, 1e-2, L_max=24)                       # M0 2^L_max = 2^27 > 2^26
     res = (ld.EstimateResult * 1)()
+    assert lib.mlmc_estimate_batch((ld.Query * 1)(q), 1, None, res) == ld.LD_EINVAL
+    q = ld.make_query(dict(ada, integrator="GL"), 1e-2)          # adaptive steps: SE only
     assert lib.mlmc_estimate_batch((ld.Query * 1)(q), 1, None, res) == ld.LD_EINVAL
