@@ -20,6 +20,7 @@ import argparse
 import hashlib
 import json
 import os
+import struct
 import sys
 import time
 
@@ -42,16 +43,56 @@ OPS_PER_COUPLED_STEP = {
     ("BAOAB", "homogeneous"): 91.0, ("GL", "homogeneous"): 84.5, ("SE", "homogeneous"): 83.5,
 }
 
-KERNEL_SOURCES = ["paper_1612_07717_amd/csrc/kernels.hip", "paper_1612_07717_amd/csrc/device_model.hpp",
-                  "paper_1612_07717_amd/csrc/device_rng.hpp", "paper_1612_07717_amd/csrc/ld_internal.hpp"]
+# The dominant kernel: the FP32 BAOAB level kernel of the neutral profile.
+DOMINANT_KERNEL = "_ZN3ldm12level_kernelIfLi2ELi1EEEvNS_5KArgsEP13ld_level_sumsPd"
 
 
-def kernel_hash() -> str:
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+def _elf_sections(blob: bytes, base: int = 0):
+    """(name, addr, offset, size) of every section of the ELF64 image at blob[base:]."""
+    shoff = struct.unpack_from("<Q", blob, base + 0x28)[0]
+    shentsize, shnum, shstrndx = struct.unpack_from("<HHH", blob, base + 0x3A)
+    raw = [struct.unpack_from("<IIQQQQ", blob, base + shoff + i * shentsize) for i in range(shnum)]
+    names_off = base + raw[shstrndx][4]
+
+    def name(o):
+        end = blob.index(b"\0", names_off + o)
+        return blob[names_off + o:end].decode()
+    return [(name(r[0]), r[3], base + r[4], r[5]) for r in raw]
+
+
+def kernel_hash(symbol: str = DOMINANT_KERNEL) -> str:
+    """sha256 (16 hex digits) of one kernel's gfx950 machine code in the built library:
+    the bytes of its symbol in the code object of the library's offload bundle. Counter
+    summaries committed under profiles/ carry it, and go stale exactly when that kernel's
+    code changes. 'missing' if the library or the kernel cannot be read."""
+    try:
+        with open(os.path.join(ROOT, "paper_1612_07717_amd", "libldmlmc.so"), "rb") as f:
+            lib = f.read()
+        fat = next(s for s in _elf_sections(lib) if s[0] == ".hip_fatbin")
+        b = fat[2]
+        if lib[b:b + 24] != b"__CLANG_OFFLOAD_BUNDLE__":
+            return "missing"
+        n = struct.unpack_from("<Q", lib, b + 24)[0]
+        pos, co = b + 32, None
+        for _ in range(n):
+            off, size, id_len = struct.unpack_from("<QQQ", lib, pos)
+            ident = lib[pos + 24:pos + 24 + id_len]
+            pos += 24 + id_len
+            if b"gfx950" in ident:
+                co = (b + off, size)
+        if co is None:
+            return "missing"
+        secs = {s[0]: s for s in _elf_sections(lib, co[0])}
+        sym, strs, text = secs[".symtab"], secs[".strtab"], secs[".text"]
+        for i in range(sym[3] // 24):
+            st_name, _, _, _, st_value, st_size = struct.unpack_from("<IBBHQQ", lib, sym[2] + 24 * i)
+            end = lib.index(b"\0", strs[2] + st_name)
+            if lib[strs[2] + st_name:end].decode() == symbol:
+                start = text[2] + (st_value - text[1])
+                return hashlib.sha256(lib[start:start + st_size]).hexdigest()[:16]
+    except (OSError, StopIteration, KeyError, struct.error, ValueError):
+        pass
+    return "missing"
 
 
 def hbm_traffic(precision: str):
