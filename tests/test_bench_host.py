@@ -1,0 +1,32 @@
+"""Host checks of bench.py's bookkeeping (no GPU).
+
+- kernel_hash finds the dominant kernel's machine code in the built library, gives
+  different hashes for different kernels and 'missing' for an unknown symbol;
+- the committed counter summaries carry a hash of the same form.
+"""
+import json
+import os
+import re
+
+import pytest
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1612_07717_amd", "libldmlmc.so")
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_kernel_hash_reads_the_code_object():
+    h32 = bench.kernel_hash()
+    h64 = bench.kernel_hash("_ZN3ldm12level_kernelIdLi2ELi1EEEvNS_5KArgsEP13ld_level_sumsPd")
+    assert re.fullmatch(r"[0-9a-f]{16}", h32) and re.fullmatch(r"[0-9a-f]{16}", h64)
+    assert h32 != h64
+    assert bench.kernel_hash("no_such_kernel") == "missing"
+
+
+def test_committed_summaries_carry_a_kernel_hash():
+    for name in ("level_kernel_fp32_single_large_traffic.json", "level_kernel_fp32_single_large_valu.json"):
+        with open(os.path.join(ROOT, "profiles", name)) as f:
+            d = json.load(f)
+        assert re.fullmatch(r"[0-9a-f]{16}", d["kernel_hash"])
