@@ -292,6 +292,41 @@ ADAPT_X = 50.0                                   # reference height X_adapt (0.0
 ADAPT_EPS_REL = (1e-2, 5e-3, 2e-3, 1e-3)
 
 
+SWEEP_EPS_REL = (1e-2, 3e-3, 1e-3)
+SWEEP_Z0 = (100.0, 500.0, 900.0)
+
+
+def sweep_report(ld):
+    """The neutral-layer estimates: release at 100, 500 or 900 m with U_0 ~ N(0,
+    sigma_U(z0)^2), T = 1000 s, M_0 = 40, levels up to 9, E[Z(T)] to a relative eps of
+    1e-2, 3e-3 or 1e-3, each integrator, FP64 and FP32 paths; wall time per
+    mlmc_estimate call (time-to-eps) and the FP32 - FP64 difference in units of eps."""
+    import torch
+    rows = []
+    for integ in ("SE", "GL", "BAOAB"):
+        ld.estimate(1e-2, W.neutral(500.0, integ), precision="fp32", eps_is_relative=True, N_init=1000, L_max=3)
+        for z0 in SWEEP_Z0:
+            cfg = W.neutral(z0, integ)
+            for eps in SWEEP_EPS_REL:
+                r = {}
+                for prec in ("fp64", "fp32"):
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    r[prec] = ld.estimate(eps, cfg, precision=prec, eps_is_relative=True, L_max=9)
+                    torch.cuda.synchronize()
+                    r[prec]["seconds"] = time.perf_counter() - t0
+                a, b = r["fp32"], r["fp64"]
+                rows.append({"integrator": integ, "z0_m": z0, "eps_rel": eps,
+                             "fp64_ms": 1e3 * b["seconds"], "fp32_ms": 1e3 * a["seconds"],
+                             "L": b["L"], "N": b["N"], "fine_steps": b["fine_steps"],
+                             "estimate_m": b["estimate"], "rmse_est_m": b["rmse_est"],
+                             "fp32_minus_fp64_over_eps": (a["estimate"] - b["estimate"]) / b["eps_abs"],
+                             "status": [a["status"], b["status"]]})
+                print(json.dumps({"progress": "sweep", **{k: v for k, v in rows[-1].items() if k != "N"}}),
+                      file=sys.stderr, flush=True)
+    return rows
+
+
 def adaptive_report(ld, precisions=("fp64", "fp32"), n_bias=1 << 22):
     """Sec. 7 set-up: the mean-position problem (release 50 m, U_0 = 0.1 m/s, T = 1000 s,
     M_0 = 40) with symplectic Euler, uniform against adaptive steps (X_adapt = 50 m):
@@ -380,7 +415,7 @@ def batched_report(ld, steps, warmup):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="single_large", choices=["single_large", "batched", "serving", "pdf", "adaptive"])
+    ap.add_argument("--workload", default="single_large", choices=["single_large", "batched", "serving", "pdf", "adaptive", "sweep"])
     ap.add_argument("--rate", type=float, default=100.0, help="serving: arrivals per second")
     ap.add_argument("--duration", type=float, default=60.0, help="serving: seconds of arrivals")
     ap.add_argument("--fifo-seconds", type=float, default=None,
@@ -445,6 +480,19 @@ def main():
                                                  "U_0 = 0.1 m/s, T = 1000 s, M_0 = 80 (SE, GL) / 40 (BAOAB)",
                                      "paper_seconds_sum": paper_s,
                                      "paper_hardware": "one core of an Intel i5-4460, the paper's C++ code"},
+                          "runs": rows}), flush=True)
+        return
+    if args.workload == "sweep":
+        rows = sweep_report(ld)
+        total64 = sum(r["fp64_ms"] for r in rows)
+        total32 = sum(r["fp32_ms"] for r in rows)
+        print(json.dumps({"metric": "time-to-eps, neutral-layer estimates (27 per precision)",
+                          "value": total32 / 1e3, "unit": "s (sum, FP32 paths)", "n_gpus": 1,
+                          "higher_is_better": False, "dtype": "f32", "data": "synthetic",
+                          "vs_baseline": None, "fp64_seconds": total64 / 1e3,
+                          "config": {"workload": "neutral layer, z0 100/500/900 m with Gaussian w0, "
+                                                 "T = 1000 s, M_0 = 40, L <= 9, relative eps "
+                                                 "1e-2/3e-3/1e-3, SE/GL/BAOAB, E[Z(T)]"},
                           "runs": rows}), flush=True)
         return
     if args.workload == "adaptive":
