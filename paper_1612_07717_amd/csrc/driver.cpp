@@ -295,7 +295,9 @@ int mlmc_estimate(double eps, const ld_qoi* qoi, ld_integrator integrator, const
         const size_t off = longb.blocks();               // the second stream's partials follow
         hipStream_t s2 = nullptr;
         hipEvent_t e_long = nullptr, e_short0 = nullptr, e_short = nullptr;
-        if (off + shortb.blocks() > slots || hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess) {
+        if (off + shortb.blocks() > slots) {
+            rc = fail(LD_ENOMEM, "early top-up: workspace too small for two batches");
+        } else if (hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess) {
             rc = fail(LD_EDEVICE, "early top-up: no second stream");
         } else {
             (void)hipEventCreate(&e_long);
