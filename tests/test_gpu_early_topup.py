@@ -62,3 +62,14 @@ def test_falls_back_to_the_plain_schedule():
         a = ld.estimate(1e-3, CFG, precision="fp64", early_topup=True, **kw)
         b = ld.estimate(1e-3, CFG, precision="fp64", **kw)
         assert a["N"] == b["N"] and a["estimate"] == b["estimate"]
+
+
+def test_adaptive_problem_with_early_topup_equals_oracle():
+    """Adaptive symplectic Euler (Sec. 7) through the early top-up schedule: the FP64
+    estimate equals the oracle's MLMC estimate over the same N_l."""
+    cfg = W.problem(integrator="SE", M0=40, x_adapt=50.0)
+    g = ld.estimate(1e-2, cfg, precision="fp64", early_topup=True, fixed_L=5, eps_is_relative=True,
+                    N_init=500)
+    est = sum(s["sum_y"] / s["n"] for s in (oracle.level_sums(cfg, l, 0, n) for l, n in enumerate(g["N"])))
+    say(f"  adaptive early top-up N={g['N']} {g['estimate']:.9f} oracle {est:.9f}")
+    assert abs(g["estimate"] - est) <= 1e-11 * abs(est)

@@ -149,3 +149,14 @@ def test_adaptive_queries_equal_single_estimates(prec):
         assert b["N"] == s["N"] and b["L"] == s["L"]
         assert b["estimate"] == s["estimate"]
         assert b["status"] == s["status"] == 1
+
+
+def test_adaptive_query_with_64_bit_ticks_equals_single_estimate():
+    """Levels 0..7 at M_0 = 40: level 7 (5120 steps) needs 64-bit tick counters, the
+    persistent kernel's other adaptive branch; the engine equals mlmc_estimate."""
+    cfg = W.problem(integrator="SE", M0=40, x_adapt=50.0)
+    q = _query(cfg, 1e-2, True, N_init=300, fixed_L=7)
+    b = ld.estimate_batch([q], precision="fp32")[0]
+    s = ld.estimate(1e-2, cfg, precision="fp32", eps_is_relative=True, N_init=300, fixed_L=7)
+    assert b["L"] == s["L"] == 7
+    assert b["N"] == s["N"] and b["estimate"] == s["estimate"]
