@@ -247,6 +247,8 @@ int mlmc_estimate(double eps, const ld_qoi* qoi, ld_integrator integrator, const
     rc = check_stability(&prob, integrator, 0);
     if (rc != LD_OK) return rc;
 
+    int device = 0;
+    if (hipGetDevice(&device) != hipSuccess) return fail(LD_ENODEVICE, "no HIP device");
     hipStream_t stream = (hipStream_t)opts.hip_stream;
     const size_t ws_need = mlmc_estimate_workspace();
     void* ws = opts.d_workspace;

@@ -282,3 +282,16 @@ def test_adaptive_steps_validation_and_stability(lib):
     assert lib.mlmc_estimate_batch((ld.Query * 1)(q), 1, None, res) == ld.LD_EINVAL
     q = ld.make_query(dict(ada, integrator="GL"), 1e-2)          # adaptive steps: SE only
     assert lib.mlmc_estimate_batch((ld.Query * 1)(q), 1, None, res) == ld.LD_EINVAL
+
+
+def test_estimate_without_a_device_reports_it(lib):
+    """Valid arguments on a machine without a GPU: LD_ENODEVICE, no crash, no fallback."""
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is present")
+    cfg = W.neutral(500.0, "BAOAB")
+    o = ld.estimate_opts(cfg, eps_is_relative=True)
+    r = ld.EstimateResult()
+    q, prof = ld.make_qoi(cfg), ld.make_profile(cfg)
+    rc = lib.mlmc_estimate(1e-2, C.byref(q), ld.INTEGRATORS["BAOAB"], C.byref(prof), C.byref(o), C.byref(r))
+    assert rc == ld.LD_ENODEVICE
