@@ -300,7 +300,8 @@ def sweep_report(ld):
     """The neutral-layer estimates: release at 100, 500 or 900 m with U_0 ~ N(0,
     sigma_U(z0)^2), T = 1000 s, M_0 = 40, levels up to 9, E[Z(T)] to a relative eps of
     1e-2, 3e-3 or 1e-3, each integrator, FP64 and FP32 paths; wall time per
-    mlmc_estimate call (time-to-eps) and the FP32 - FP64 difference in units of eps."""
+    mlmc_estimate call (time-to-eps) and the FP32 - FP64 difference in units of eps; and
+    standard Monte Carlo (one level) on the finest step the MLMC run needed, FP32."""
     import torch
     rows = []
     for integ in ("SE", "GL", "BAOAB"):
@@ -316,12 +317,22 @@ def sweep_report(ld):
                     torch.cuda.synchronize()
                     r[prec]["seconds"] = time.perf_counter() - t0
                 a, b = r["fp32"], r["fp64"]
+                # standard Monte Carlo on the finest step the MLMC run used (one level of
+                # M_0 2^L steps, N by the variance rule), FP32 paths
+                st_cfg = dict(cfg, M0=int(cfg["M0"]) << b["L"])
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                st = ld.estimate(eps, st_cfg, precision="fp32", eps_is_relative=True, fixed_L=0)
+                torch.cuda.synchronize()
+                t_st = time.perf_counter() - t0
                 rows.append({"integrator": integ, "z0_m": z0, "eps_rel": eps,
                              "fp64_ms": 1e3 * b["seconds"], "fp32_ms": 1e3 * a["seconds"],
                              "L": b["L"], "N": b["N"], "fine_steps": b["fine_steps"],
                              "estimate_m": b["estimate"], "rmse_est_m": b["rmse_est"],
                              "fp32_minus_fp64_over_eps": (a["estimate"] - b["estimate"]) / b["eps_abs"],
-                             "status": [a["status"], b["status"]]})
+                             "stmc_fp32_ms": 1e3 * t_st, "stmc_fine_steps": st["fine_steps"],
+                             "stmc_N": st["N"][0], "stmc_estimate_m": st["estimate"],
+                             "status": [a["status"], b["status"], st["status"]]})
                 print(json.dumps({"progress": "sweep", **{k: v for k, v in rows[-1].items() if k != "N"}}),
                       file=sys.stderr, flush=True)
     return rows
