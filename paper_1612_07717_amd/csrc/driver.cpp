@@ -311,7 +311,7 @@ int mlmc_estimate(double eps, const ld_qoi* qoi, ld_integrator integrator, const
             ld_level_sums h_long[LD_MAX_LEVELS], h_short[LD_MAX_LEVELS], h_top[LD_MAX_LEVELS];
             if (timing) (void)hipEventRecord(ev0, stream);
             rc = run_batch(&prob, integrator, opts.precision, longb.r, longb.n, d_sums, d_partials,
-                           partial_bytes, nullptr, stream);
+                           off * sizeof(ld_level_sums), nullptr, stream);
             if (rc == LD_OK && e_long) (void)hipEventRecord(e_long, stream);
             // kernel time of the second stream: each of its batches between two events
             double s2_seconds = 0.0;
