@@ -97,9 +97,34 @@ struct Math<float> {
 
 template <>
 struct Math<double> {
-    static __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
-    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
-    static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / sqrt(x); }
+    // Square root, reciprocal and reciprocal square root for the path arithmetic, whose
+    // arguments are finite, non-negative and far from the range ends (heights, step
+    // sizes, rates): the hardware estimate refined by Newton steps, without the range
+    // scaling of the library routines. sqrt: s = x r, h = r/2 from r = rsq(x), one
+    // coupled Newton step on (s, h), then two corrections s += (x - s^2) h; the argument is
+    // raised to the least normal number first so that sqrt(0) = 0. rcp: two Newton steps
+    // r += r (1 - x r). Both are within an ulp or so of the correctly rounded result.
+    static __device__ __forceinline__ double sqrt_(double x) {
+        const double xs = fmax(x, 2.2250738585072014e-308);
+        const double r = __builtin_amdgcn_rsq(xs);
+        double s = x * r, h = 0.5 * r;
+        const double e = fma(-s, h, 0.5);
+        s = fma(s, e, s);
+        h = fma(h, e, h);
+        s = fma(fma(-s, s, x), h, s);
+        return fma(fma(-s, s, x), h, s);
+    }
+    static __device__ __forceinline__ double rcp(double x) {
+        double r = __builtin_amdgcn_rcp(x);
+        r = fma(r, fma(-x, r, 1.0), r);
+        return fma(r, fma(-x, r, 1.0), r);
+    }
+    static __device__ __forceinline__ double rsqrt(double x) {
+        const double r = __builtin_amdgcn_rsq(x);                 // x > 0
+        const double hr = 0.5 * r;
+        const double y = fma(-hr, x * r, 1.5) * r;                 // r (3 - x r^2) / 2
+        return fma(-0.5 * y, x * y, 1.5) * y;
+    }
     static __device__ __forceinline__ double flip(double v, uint32_t mask) {
         return __hiloint2double(__double2hiint(v) ^ (int)mask, __double2loint(v));
     }
@@ -122,8 +147,8 @@ struct Math<double> {
         return fmin(fmax(x, lo), hi);
     }
     static __device__ __forceinline__ void sqrt_and_rcp(double d, double& sq, double& inv) {
-        sq = sqrt(d);
-        inv = 1.0 / d;
+        sq = sqrt_(d);
+        inv = rcp(d);
     }
     static __device__ __forceinline__ bool outside(double x, double H) { return x < 0.0 || x > H; }
 
