@@ -219,10 +219,10 @@ typedef struct {
     int32_t max_iter;        /* default 100 */
     int32_t early_topup;     /* nonzero (and L_min or fixed_L >= 5): the first batch of the
                                 short levels 0..L0-5 runs on a second stream beside the long
-                                levels', and 0.9 of the samples the variance rule asks of the
-                                short levels alone is drawn at once, before the long levels
-                                end (default 0). Same draws, other sample counts N_l than
-                                the plain schedule; the plain MLMC estimate of what is drawn */
+                                levels', and the samples the variance rule asks of the short
+                                levels alone are drawn at once, before the long levels end
+                                (default 0). Same draws, other sample counts N_l than the
+                                plain schedule; the plain MLMC estimate of what is drawn */
     double x_adapt;          /* symplectic Euler: adaptive steps below this height (0 = off) */
     double max_fine_steps;   /* cost budget: stop (LD_WARN_NOT_CONVERGED) rather than draw
                                 a batch that would take sum_l N_l M_l above this; the

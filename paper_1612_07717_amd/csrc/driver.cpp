@@ -96,13 +96,14 @@ void merge_into(HostSums& acc, const ld_level_sums& add) {
 // batch on the caller's stream, the short ones theirs on a second stream. As soon as the
 // short levels' sums are back, the variance rule is applied to them alone: with the sum
 // of sqrt(V_k C_k) over the short levels only, each N_l is at most what the full rule will
-// ask once the long levels are known (for an absolute eps). kEarlyFraction of it is drawn
-// at once, on the second stream, while the long levels still run; the ordinary
-// iterations follow. The draws are the same (sample indices from 0 upward on every
+// ask once the long levels are known (for an absolute eps; for a relative one the short
+// levels' partial estimate stands in, and the long levels' corrections are small). That
+// many (kEarlyFraction of it) are drawn at once, on the second stream, while the long
+// levels still run; the ordinary iterations follow, usually with little left to draw. The draws are the same (sample indices from 0 upward on every
 // level), only their order in time changes, so the estimate is the plain MLMC estimate
 // of whatever N_l end up drawn.
 constexpr int32_t kEarlyGap = 5;
-constexpr double kEarlyFraction = 0.9;
+constexpr double kEarlyFraction = 1.0;
 
 struct Batch {
     ld_level_range r[LD_MAX_LEVELS];
