@@ -16,10 +16,12 @@ SOURCES = ["kernels.hip", "api.cpp", "driver.cpp", "engine.cpp", "server.cpp", "
 
 # -packed-fp32-ops: never emit v_pk_{add,mul,fma}_f32 (packed FP32 has given silent
 # wrong results on these boxes). No fast-math: the compensated sums and the expm1-based
-# O-step rely on IEEE semantics.
+# O-step rely on IEEE semantics. -ffp-contract=on: a multiply feeds an add as one FMA only
+# within one source expression (a * b + c), never across statements, so every inlined
+# copy of a step rounds alike (HIP's default, fast, lets the backend choose per context).
 HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
                "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-               "-fno-fast-math", "-Wall", "-Wno-unused-function"]
+               "-fno-fast-math", "-ffp-contract=on", "-Wall", "-Wno-unused-function"]
 
 
 def hipcc() -> str:

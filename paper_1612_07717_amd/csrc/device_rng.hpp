@@ -82,7 +82,7 @@ __device__ __forceinline__ float uniform32(uint32_t hi) {
 template <typename R>
 struct Normals;
 
-// ln u for u = (2m + 1) 2^-53 in (0, 1), to about half an ulp. With u = m 2^e and m in
+// ln u for u = (2j + 1) 2^-53 in (0, 1), to about half an ulp. With u = m 2^e and m in
 // [sqrt(1/2), sqrt(2)): ln u = e ln 2 + 2 atanh(s), s = (m - 1) / (m + 1), |s| <= 0.1716,
 // and 2 atanh(s) = 2s + 2s t (1/3 + t/5 + ... + t^9/21), t = s^2 (the next term is below
 // 1e-18 relative). s = q + sl: q the rounded quotient, sl from its exact residual (m + 1

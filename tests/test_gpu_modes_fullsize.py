@@ -2,7 +2,8 @@
 
 - A level range small enough for the wave-specialised (PIPE) blocks and the same range
   extended past that size (STREAM blocks) give bitwise identical per-sample results:
-  both modes run the same arithmetic on the same draws.
+  both modes run the same arithmetic on the same draws, in the neutral layer and in
+  homogeneous turbulence whose steps cross the whole layer.
 - Full size: the single large estimate (neutral layer, BAOAB, dt_0 = T/8, levels
   0..12, relative eps 1e-4) in the launch configuration the benchmark times; sampled
   outputs are recomputed one by one by the oracle.
@@ -43,6 +44,31 @@ def test_pipe_and_stream_blocks_agree_bitwise(integ, prec):
     y = ref[:, 0] - ref[:, 1]
     assert s_pipe["n"] == 777
     assert abs(s_pipe["sum_y"] - y.sum()) <= 1e-12 * np.abs(y).sum()
+
+
+@pytest.mark.parametrize("H", [100.0, 400.0])
+@pytest.mark.parametrize("integ,prec", [("BAOAB", "fp32"), ("SE", "fp64"), ("GL", "fp64"), ("BAOAB", "fp64")])
+def test_pipe_and_stream_agree_when_steps_cross_the_layer(integ, prec, H):
+    """Homogeneous turbulence with sigma_w = 40 m/s and h = 3.125 s on level 3 (PIPE
+    blocks, since M_3 = 320): with H = 100 m about 40 % of the steps are longer than the
+    layer and fold by several reflections; with H = 400 m about a tenth of the samples
+    have such a step (a plain OU simulation of the velocity gives 9.5 %). The two block
+    modes agree bitwise, and FP64 paths match the oracle. A position's rounding error
+    grows with the distance its path travels (about sigma_w T = 40 km here, some 10^2
+    crossings of the layer) rather than with where it ends, so the scale below a
+    position's magnitude is H itself instead of 10^-3 H."""
+    cfg = W.homogeneous(H=H, sigma_u=40.0, z0=0.5 * H, M0=40, integrator=integ)
+    say(f"case steps across the layer {integ} {prec} H={H}")
+    pipe = ld.level_samples(cfg, 3, 5, PIPE_MAX, prec)
+    stream = ld.level_samples(cfg, 3, 5, PIPE_MAX + 1, prec)
+    diff = np.flatnonzero(np.any(pipe != stream[:PIPE_MAX], axis=1))
+    assert diff.size == 0, (diff.size, diff[:8].tolist(), pipe[diff[:4]].tolist(), stream[diff[:4]].tolist())
+    assert np.all((pipe >= 0.0) & (pipe <= H))
+    if prec == "fp64":
+        ref = oracle.level_samples(cfg, 3, 5, 700)
+        err = np.abs(pipe[:700] - ref)
+        say(f"  max |GPU - oracle| {err.max():.2e} m")
+        assert np.all(err <= 1e-12 * np.maximum(np.abs(ref), H)), err.max()
 
 
 def _sampled_parity(cfg, level, n, prec, k=48, seed=0):
