@@ -295,3 +295,15 @@ def test_estimate_without_a_device_reports_it(lib):
     q, prof = ld.make_qoi(cfg), ld.make_profile(cfg)
     rc = lib.mlmc_estimate(1e-2, C.byref(q), ld.INTEGRATORS["BAOAB"], C.byref(prof), C.byref(o), C.byref(r))
     assert rc == ld.LD_ENODEVICE
+
+
+def test_device_code_flags_fix_the_rounding():
+    """PIPE and STREAM blocks inline the same step and must round alike, so an FMA comes
+    only from a * b + c within one expression (-ffp-contract=on, not HIP's 'fast');
+    no fast-math (the compensated sums need IEEE semantics); packed FP32 stays off."""
+    from paper_1612_07717_amd import build
+    f = build.HIPCC_FLAGS
+    assert "-ffp-contract=on" in f and "-fno-fast-math" in f
+    assert not any(x.startswith("-ffast-math") or x == "-ffp-contract=fast" for x in f)
+    i = f.index("-packed-fp32-ops")
+    assert f[i - 1] == "-Xclang" and f[i - 2] == "-target-feature" and f[i - 3] == "-Xclang"
