@@ -123,22 +123,48 @@ def valu_issue(precision: str):
     return {f"{r['blocks']}_blocks": round(r["issue_frac"], 3) for r in d["launches"] if r.get("issue_frac")}
 
 
-def cpu_baseline(cfg, N_levels, target_steps=2.5e8):
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(cfg, N_levels, target_steps=2.5e8, one_core_steps=1.2e7):
     """The oracle on a bounded sample: each level's samples scaled down by the same
-    factor so the sample has about target_steps coupled fine steps."""
+    factor so the sample has about target_steps coupled fine steps, on all of the
+    oracle's threads; then a smaller sample of the same shape on one thread (the figure
+    to set beside the paper's single-core timings)."""
     import oracle
-    total = sum(n * (cfg["M0"] << l) for l, n in enumerate(N_levels))
-    f = min(1.0, target_steps / total)
-    counts = [max(64, int(n * f)) for n in N_levels]
-    steps = sum(n * (cfg["M0"] << l) for l, n in enumerate(counts))
-    t0 = time.perf_counter()
-    for l, n in enumerate(counts):
-        oracle.level_sums(cfg, l, 0, n)
-    dt = time.perf_counter() - t0
-    return {"value": steps / dt, "unit": "coupled particle-steps/s", "cores": oracle.num_threads(),
+
+    def run(steps_wanted):
+        total = sum(n * (cfg["M0"] << l) for l, n in enumerate(N_levels))
+        f = min(1.0, steps_wanted / total)
+        counts = [max(64, int(n * f)) for n in N_levels]
+        steps = sum(n * (cfg["M0"] << l) for l, n in enumerate(counts))
+        t0 = time.perf_counter()
+        for l, n in enumerate(counts):
+            oracle.level_sums(cfg, l, 0, n)
+        return f, counts, steps, time.perf_counter() - t0
+
+    threads = oracle.num_threads()
+    f, counts, steps, dt = run(target_steps)
+    oracle.set_num_threads(1)
+    try:
+        f1, _, steps1, dt1 = run(one_core_steps)
+    finally:
+        oracle.set_num_threads(threads)
+    return {"value": steps / dt, "unit": "coupled particle-steps/s", "cores": threads,
             "kind": "oracle",
             "sample": f"levels 0..{len(counts) - 1} of the same workload with N_l scaled by "
-                      f"{f:.3g} (N_l = {counts}), {steps:.3g} coupled fine steps, FP64, {dt:.1f} s"}
+                      f"{f:.3g} (N_l = {counts}), {steps:.3g} coupled fine steps, FP64, {dt:.1f} s",
+            "one_core": {"value": steps1 / dt1, "sample": f"N_l scaled by {f1:.3g}, {steps1:.3g} "
+                                                          f"coupled fine steps, {dt1:.1f} s"},
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count()}
 
 
 def _pct(xs, q):
@@ -551,6 +577,9 @@ def main():
 
     fine_steps = sum(r["fine_steps"] for r in results)
     value = fine_steps / elapsed
+    # every integrator step, fine and coarse: sum_l N_l (M_l + M_{l-1}), M_{-1} = 0
+    integ_steps = sum(n * ((cfg["M0"] << l) + ((cfg["M0"] << l) >> 1 if l > 0 else 0))
+                      for r in results for l, n in enumerate(r["N"]))
 
     # The same estimate with all-FP64 paths (time-to-eps), and the FP32 run's error
     # against FP64 paths on identical draws and sample counts.
@@ -588,6 +617,7 @@ def main():
                    "schedule": "plain" if args.plain_schedule else "early top-up (short levels beside the long ones)",
                    "levels": L + 1, "N_l": last["N"], "fine_steps_per_step": last["fine_steps"],
                    "estimate_m": last["estimate"], "rmse_est_m": last["rmse_est"],
+                   "integrator_steps_per_s": integ_steps / elapsed,
                    "time_to_eps_s": last["wall_seconds"], "kernel_s_per_step": dev_s / args.steps,
                    "launches_per_step": launches / args.steps,
                    f"time_to_eps_{other}_s": t_other,

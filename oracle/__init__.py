@@ -158,6 +158,8 @@ def load():
     lib.oracle_estimate_pdf.argtypes = [C.c_double, P(Problem), P(Opts), C.c_double, C.c_double,
                                         C.c_int32, C.c_int32, P(PdfResult)]
     lib.oracle_num_threads.restype = C.c_int
+    lib.oracle_set_num_threads.argtypes = [C.c_int]
+    lib.oracle_set_num_threads.restype = None
     _lib = lib
     return lib
 
@@ -353,3 +355,8 @@ def estimate_pdf(eps, cfg, a0, width, n_bins, *, estimator=MLMC, L_min=2, L_max=
 
 def num_threads() -> int:
     return int(load().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of later oracle calls; the results do not depend on it."""
+    load().oracle_set_num_threads(int(n))

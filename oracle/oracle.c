@@ -1026,3 +1026,12 @@ int oracle_num_threads(void) {
     return 1;
 #endif
 }
+
+/* Threads of the following parallel loops (n >= 1); results do not depend on it. */
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

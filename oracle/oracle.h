@@ -226,6 +226,8 @@ int oracle_estimate_pdf(double eps, const oracle_problem* p, const oracle_opts* 
                         oracle_pdf_result* out);
 
 int oracle_num_threads(void);
+/* Sets the OpenMP threads of later calls (n >= 1); results do not depend on it. */
+void oracle_set_num_threads(int n);
 
 #ifdef __cplusplus
 }

@@ -70,6 +70,19 @@ def test_level_sums_are_split_invariant(orc):
         assert b1[k] + b2[k] == pytest.approx(a[k], rel=1e-14)
 
 
+def test_level_sums_do_not_depend_on_the_thread_count(orc):
+    """Fixed-order chunks: one thread and all threads give the same bits."""
+    p = W.neutral(300.0, "GL")
+    many = orc.num_threads()
+    a = orc.level_sums(p, 2, 3, 4000)
+    orc.set_num_threads(1)
+    try:
+        b = orc.level_sums(p, 2, 3, 4000)
+    finally:
+        orc.set_num_threads(many)
+    assert a == b
+
+
 def test_plan_first_batch_and_variance_rule(orc):
     """N_l = ceil(2 eps^-2 sqrt(V_l/C_l) sum_k sqrt(V_k C_k)) after a first batch."""
     rng = np.random.default_rng(3)
