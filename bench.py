@@ -416,7 +416,7 @@ def batched_report(ld, steps, warmup):
     spec = W.batched_estimators(64)
     queries = [ld.make_query(q["problem"], q["eps"], eps_is_relative=q["eps_is_relative"],
                              N_init=BATCHED_N_INIT) for q in spec]
-    best, t_tune = ld.autotune(queries, reps=1, precision="fp32")
+    best, t_tune = ld.autotune(queries, reps=3, precision="fp32")   # median of 3 per configuration
     res = {}
     for prec in ("fp32", "fp64"):
         o = ld.engine_opts(**dict(ld.opts_dict(best), precision=prec))
