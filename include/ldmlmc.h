@@ -415,8 +415,8 @@ int mlmc_estimate_batch(const ld_query* queries, int32_t n, const ld_engine_opts
 /* Autotuner: times the batch `queries` on engines with each candidate persistent grid
    (blocks_per_cu in {2, 4, 6, 8, 12, 16}) and tile policy (target_tiles in
    {4096, 8192, 16384, 32768, 65536}, wave-specialised tiles on/off), keeps the
-   fastest, and writes it to *best (other fields from base). reps timings per
-   candidate, the median counts. */
+   fastest, and writes it to *best (other fields from base). Each candidate gets one
+   engine, created outside its timings; reps timings per candidate, the median counts. */
 int ld_engine_autotune(const ld_query* queries, int32_t n, const ld_engine_opts* base,
                        int32_t reps, ld_engine_opts* best, double* best_seconds);
 

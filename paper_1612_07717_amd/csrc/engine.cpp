@@ -570,16 +570,10 @@ int ld_engine_stats(ld_engine* e, double* device_seconds, int64_t* iterations, d
     return LD_OK;
 }
 
-int mlmc_estimate_batch(const ld_query* queries, int32_t n, const ld_engine_opts* opts,
-                        ld_estimate_result* out) {
-    if (queries == nullptr || out == nullptr || n < 1) return fail(LD_EINVAL, "need n >= 1 queries");
-    for (int32_t i = 0; i < n; ++i) {
-        const int rc = validate_query(&queries[i]);
-        if (rc != LD_OK) return rc;
-    }
-    ld_engine* e = nullptr;
-    int rc = ld_engine_create(opts, &e);
-    if (rc != LD_OK) return rc;
+// Submits queries[0..n) to an engine as slots free up and steps it until every one has a
+// result in out[]; releases each handle. Returns the worst status (an error, else a
+// warning, else LD_OK). On an error the engine may still hold admitted queries.
+static int run_to_completion(ld_engine* e, const ld_query* queries, int32_t n, ld_estimate_result* out) {
     std::vector<int64_t> handle(n, -1);
     std::vector<bool> got(n, false);
     int32_t next = 0, remaining = n;
@@ -589,18 +583,12 @@ int mlmc_estimate_batch(const ld_query* queries, int32_t n, const ld_engine_opts
             int64_t h;
             const int s = ld_engine_submit(e, &queries[next], &h);
             if (s == LD_EBUSY) break;
-            if (s != LD_OK) {
-                ld_engine_destroy(e);
-                return s;
-            }
+            if (s != LD_OK) return s;
             handle[next++] = h;
         }
         int32_t active = 0;
-        rc = ld_engine_step(e, &active);
-        if (rc != LD_OK) {
-            ld_engine_destroy(e);
-            return rc;
-        }
+        const int rc = ld_engine_step(e, &active);
+        if (rc != LD_OK) return rc;
         for (int32_t i = 0; i < next; ++i) {
             if (got[i]) continue;
             const int s = ld_engine_result(e, handle[i], &out[i]);
@@ -612,8 +600,22 @@ int mlmc_estimate_batch(const ld_query* queries, int32_t n, const ld_engine_opts
             if (s > 0 && worst == LD_OK) worst = s;
         }
     }
-    ld_engine_destroy(e);
     return worst;
+}
+
+int mlmc_estimate_batch(const ld_query* queries, int32_t n, const ld_engine_opts* opts,
+                        ld_estimate_result* out) {
+    if (queries == nullptr || out == nullptr || n < 1) return fail(LD_EINVAL, "need n >= 1 queries");
+    for (int32_t i = 0; i < n; ++i) {
+        const int rc = validate_query(&queries[i]);
+        if (rc != LD_OK) return rc;
+    }
+    ld_engine* e = nullptr;
+    const int rc = ld_engine_create(opts, &e);
+    if (rc != LD_OK) return rc;
+    const int r = run_to_completion(e, queries, n, out);
+    ld_engine_destroy(e);
+    return r;
 }
 
 int ld_engine_autotune(const ld_query* queries, int32_t n, const ld_engine_opts* base, int32_t reps,
@@ -638,13 +640,22 @@ int ld_engine_autotune(const ld_query* queries, int32_t n, const ld_engine_opts*
                 o.blocks_per_cu = g;
                 o.target_tiles = t;
                 o.pipe_max_samples = pm;
+                // one engine per configuration, so that its allocation stays out of the
+                // timings (as for a server, which keeps its engine)
+                ld_engine* e = nullptr;
+                int rc = ld_engine_create(&o, &e);
+                if (rc != LD_OK) return rc;
                 std::vector<double> times;
                 for (int32_t r = 0; r < reps; ++r) {
                     const double t0 = now_seconds();
-                    const int rc = mlmc_estimate_batch(queries, n, &o, res.data());
-                    if (rc < 0 && rc != LD_ENONFINITE) return rc;
+                    rc = run_to_completion(e, queries, n, res.data());
+                    if (rc < 0 && rc != LD_ENONFINITE) {
+                        ld_engine_destroy(e);
+                        return rc;
+                    }
                     times.push_back(now_seconds() - t0);
                 }
+                ld_engine_destroy(e);
                 std::sort(times.begin(), times.end());
                 const double med = times[times.size() / 2];
                 if (med < best_t) {
