@@ -335,12 +335,18 @@ typedef struct {
    be 0). LD_STMC: standard Monte Carlo (Sec. 3.2) on the single fine path of step
    T / (M0 2^L), L = opts.fixed_L (>= 0): opts.N_init samples, then
    N = ceil(2 max_i Var[P_i] / eps^2), topped up while that exceeds the samples drawn
-   by more than 1 %. Blocks until done; opts.d_workspace is not used (the call
-   allocates and frees its own). */
+   by more than 1 %. Blocks until done. opts.d_workspace: a caller-owned DEVICE buffer
+   of at least mlmc_estimate_pdf_workspace(bins->n_bins) bytes (opts.workspace_bytes;
+   LD_ENOMEM if smaller), used on opts.hip_stream; NULL: the call allocates and frees
+   its own. */
 int mlmc_estimate_pdf(double eps, const ld_bins* bins, const ld_qoi* qoi,
                       ld_integrator integrator, const ld_profile* profile,
                       const ld_estimate_opts* opts, ld_estimator estimator,
                       ld_pdf_result* out);
+
+/* Bytes of the device workspace mlmc_estimate_pdf uses for n_bins bins (0 if n_bins is
+   outside 1..LD_MAX_BINS). */
+size_t mlmc_estimate_pdf_workspace(int32_t n_bins);
 
 /* ---- many estimators at once: the engine ---------------------------------------- */
 

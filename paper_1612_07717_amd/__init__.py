@@ -31,7 +31,7 @@ EXPORTED = ["mlmc_level_sums_workspace", "mlmc_level_sums", "mlmc_level_sums_bat
             "ld_engine_default_opts", "ld_engine_create", "ld_engine_destroy", "ld_engine_submit",
             "ld_engine_step", "ld_engine_result", "ld_engine_release", "ld_engine_stats",
             "mlmc_pdf_level_sums_workspace", "mlmc_pdf_level_sums", "mlmc_plan_pdf",
-            "mlmc_estimate_pdf",
+            "mlmc_estimate_pdf", "mlmc_estimate_pdf_workspace",
             "mlmc_estimate_batch", "ld_engine_autotune",
             "ld_server_default_opts", "ld_server_create", "ld_server_destroy", "ld_server_submit",
             "ld_server_wait", "ld_server_stats_get", "ld_server_clock",
@@ -241,6 +241,8 @@ def load():
     lib.mlmc_plan_pdf.argtypes = [P(PdfPlanIn), P(PdfPlanOut)]
     lib.mlmc_estimate_pdf.argtypes = [C.c_double, P(Bins), P(Qoi), C.c_int, P(Profile),
                                       P(EstimateOpts), C.c_int, P(PdfResult)]
+    lib.mlmc_estimate_pdf_workspace.argtypes = [C.c_int32]
+    lib.mlmc_estimate_pdf_workspace.restype = C.c_size_t
     lib.ld_server_default_opts.argtypes = [P(ServerOpts)]
     lib.ld_server_default_opts.restype = None
     lib.ld_server_create.argtypes = [P(ServerOpts), P(C.c_void_p)]
@@ -403,8 +405,15 @@ def estimate_workspace_bytes() -> int:
 
 
 def estimate(eps, cfg, **kw) -> dict:
-    """mlmc_estimate(eps, qoi, integrator, profile) with options from cfg and kw."""
+    """mlmc_estimate(eps, qoi, integrator, profile) with options from cfg and kw. Without
+    a workspace, one comes from PyTorch's caching allocator on the current stream, so
+    repeated calls do not each allocate and free it on the device (mlmc_estimate returns
+    only after its work on that stream is done)."""
     lib = load()
+    if kw.get("workspace") is None:
+        import torch
+        if torch.cuda.is_available():   # else the library reports the missing device itself
+            kw["workspace"] = torch.empty(estimate_workspace_bytes(), dtype=torch.uint8, device="cuda")
     o = estimate_opts(cfg, **kw)
     r = EstimateResult()
     q, prof = make_qoi(cfg), make_profile(cfg)
@@ -621,10 +630,14 @@ def pdf_plan(d: dict) -> dict:
 
 
 def estimate_pdf(eps, cfg, a0, width, n_bins, *, estimator="mlmc", stream=None, **kw) -> dict:
-    """mlmc_estimate_pdf: binned concentration to absolute RMSE eps per bin."""
-    _torch()
+    """mlmc_estimate_pdf: binned concentration to absolute RMSE eps per bin. Without a
+    workspace, one comes from PyTorch's caching allocator on the current stream."""
+    torch = _torch()
     lib = load()
     kw.setdefault("eps_is_relative", False)
+    if kw.get("workspace") is None:
+        kw["workspace"] = torch.empty(int(lib.mlmc_estimate_pdf_workspace(int(n_bins))),
+                                      dtype=torch.uint8, device="cuda")
     o = estimate_opts(cfg, stream=stream, **kw)
     r = PdfResult()
     b = make_bins(a0, width, n_bins)

@@ -137,6 +137,11 @@ size_t mlmc_pdf_level_sums_workspace(uint64_t n_samples, int32_t n_bins) {
     return pdf_layout(n_samples, n_bins).total;
 }
 
+size_t mlmc_estimate_pdf_workspace(int32_t n_bins) {
+    if (n_bins < 1 || n_bins > LD_MAX_BINS) return 0;
+    return pdf_layout(kChunk, n_bins).total + align256((size_t)n_bins * sizeof(ld_level_sums));
+}
+
 int mlmc_pdf_level_sums(const ld_problem* problem, ld_integrator integrator, ld_precision precision,
                         int32_t level, uint64_t sample_begin, uint64_t n_samples, const ld_bins* bins,
                         ld_level_sums* d_out, void* d_workspace, size_t workspace_bytes, void* hip_stream) {
@@ -259,8 +264,14 @@ int mlmc_estimate_pdf(double eps, const ld_bins* bins, const ld_qoi* qoi, ld_int
     const PdfWs lay = pdf_layout(kChunk, k);
     char* ws = nullptr;
     ld_level_sums* d_out = nullptr;
-    if (hipMalloc((void**)&ws, lay.total) != hipSuccess ||
-        hipMalloc((void**)&d_out, (size_t)k * sizeof(ld_level_sums)) != hipSuccess) {
+    const bool own_ws = opts.d_workspace == nullptr;
+    if (!own_ws) {
+        if (opts.workspace_bytes < mlmc_estimate_pdf_workspace(k))
+            return fail(LD_ENOMEM, "workspace smaller than mlmc_estimate_pdf_workspace()");
+        ws = (char*)opts.d_workspace;
+        d_out = (ld_level_sums*)(ws + lay.total);
+    } else if (hipMalloc((void**)&ws, lay.total) != hipSuccess ||
+               hipMalloc((void**)&d_out, (size_t)k * sizeof(ld_level_sums)) != hipSuccess) {
         if (ws) (void)hipFree(ws);
         return fail(LD_EDEVICE, "hipMalloc of the workspace failed");
     }
@@ -367,8 +378,10 @@ int mlmc_estimate_pdf(double eps, const ld_bins* bins, const ld_qoi* qoi, ld_int
         (void)hipEventDestroy(ev0);
         (void)hipEventDestroy(ev1);
     }
-    (void)hipFree(ws);
-    (void)hipFree(d_out);
+    if (own_ws) {
+        (void)hipFree(ws);
+        (void)hipFree(d_out);
+    }
     if (rc != LD_OK) return rc;
     out->iterations = iter;
     out->device_seconds = device_s;

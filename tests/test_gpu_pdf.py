@@ -100,3 +100,28 @@ def test_range_longer_than_a_chunk():
     for i, x in enumerate(whole):
         assert x["n"] == n
         assert st["estimate"][i] == pytest.approx(x["sum_pf"] / x["n"], rel=1e-12, abs=1e-15)
+
+
+def test_estimate_pdf_with_a_caller_workspace_or_its_own():
+    """A caller's workspace (what the binding passes) and the library's own allocation
+    (NULL through the C ABI) give the same estimate bit for bit; a workspace below
+    mlmc_estimate_pdf_workspace() is refused with LD_ENOMEM."""
+    import ctypes as C
+    import torch
+    cfg = W.neutral(200.0, "BAOAB", r=4, delta=100.0, M0=40)
+    kw = dict(N_init=1000, L_max=6, precision="fp64")
+    g = ld.estimate_pdf(1e-2, cfg, 0.0, 100.0, 10, **kw)
+    lib = ld.load()
+    o = ld.estimate_opts(cfg, eps_is_relative=False, **kw)      # d_workspace NULL
+    r = ld.PdfResult()
+    rc = lib.mlmc_estimate_pdf(1e-2, C.byref(ld.make_bins(0.0, 100.0, 10)), C.byref(ld.make_qoi(cfg)),
+                               ld.INTEGRATORS["BAOAB"], C.byref(ld.make_profile(cfg)), C.byref(o),
+                               ld.ESTIMATORS["mlmc"], C.byref(r))
+    assert rc in (ld.LD_OK, ld.LD_WARN_NOT_CONVERGED)
+    assert [int(r.N[l]) for l in range(r.L + 1)] == g["N"]
+    assert list(r.estimate[:10]) == g["estimate"]
+    need = int(lib.mlmc_estimate_pdf_workspace(10))
+    small = torch.empty(need - 256, dtype=torch.uint8, device="cuda")
+    with pytest.raises(ld.LdError) as e:
+        ld.estimate_pdf(1e-2, cfg, 0.0, 100.0, 10, workspace=small, **kw)
+    assert e.value.status == ld.LD_ENOMEM
