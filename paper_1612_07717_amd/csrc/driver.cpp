@@ -300,12 +300,8 @@ int mlmc_estimate(double eps, const ld_qoi* qoi, ld_integrator integrator, const
         hipEvent_t e_long = nullptr, e_short0 = nullptr, e_short = nullptr;
         if (off + shortb.blocks() > slots) {
             rc = fail(LD_ENOMEM, "early top-up: workspace too small for two batches");
-        } else if (hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess) {
-            rc = fail(LD_EDEVICE, "early top-up: no second stream");
         } else {
             (void)hipEventCreate(&e_long);
-            (void)hipEventCreate(&e_short0);
-            (void)hipEventCreate(&e_short);
             ld_level_sums* d_sums2 = d_sums + longb.n;
             void* d_part2 = (void*)((ld_level_sums*)d_partials + off);
             const size_t part2_bytes = partial_bytes - off * sizeof(ld_level_sums);
@@ -314,6 +310,15 @@ int mlmc_estimate(double eps, const ld_qoi* qoi, ld_integrator integrator, const
             rc = run_batch(&prob, integrator, opts.precision, longb.r, longb.n, d_sums, d_partials,
                            off * sizeof(ld_level_sums), nullptr, stream);
             if (rc == LD_OK && e_long) (void)hipEventRecord(e_long, stream);
+            // the long levels run first; the second stream and its events are made meanwhile
+            if (rc == LD_OK && hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess) {
+                s2 = nullptr;
+                rc = fail(LD_EDEVICE, "early top-up: no second stream");
+            }
+            if (rc == LD_OK) {
+                (void)hipEventCreate(&e_short0);
+                (void)hipEventCreate(&e_short);
+            }
             // kernel time of the second stream: each of its batches between two events
             double s2_seconds = 0.0;
             auto s2_span = [&]() {
@@ -390,6 +395,10 @@ int mlmc_estimate(double eps, const ld_qoi* qoi, ld_integrator integrator, const
                 }
                 std::memset(dn, 0, sizeof dn);               // the loop below starts by planning
             }
+        }
+        if (rc != LD_OK) {   // work already queued may still use the workspace
+            (void)hipStreamSynchronize(stream);
+            if (s2) (void)hipStreamSynchronize(s2);
         }
         if (e_long) (void)hipEventDestroy(e_long);
         if (e_short0) (void)hipEventDestroy(e_short0);
