@@ -252,6 +252,10 @@ def test_pdf_arguments_rejected_without_device(lib):
                                    None) == ld.LD_ENOMEM
     assert lib.mlmc_pdf_level_sums_workspace(1000, 0) == 0
     assert lib.mlmc_pdf_level_sums_workspace(1000, 20) >= 16 * 1000
+    assert lib.mlmc_estimate_pdf_workspace(0) == 0 and lib.mlmc_estimate_pdf_workspace(65) == 0
+    # the estimate's workspace holds a whole dump chunk (16 B per sample) and the sums of
+    # every bin, and grows with the bin count
+    assert lib.mlmc_estimate_pdf_workspace(64) > lib.mlmc_estimate_pdf_workspace(1) >= 16 << 22
     res = ld.PdfResult()
     q, prof = ld.make_qoi(cfg), ld.make_profile(cfg)
     o = ld.estimate_opts(cfg)
