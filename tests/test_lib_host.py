@@ -266,6 +266,10 @@ def test_pdf_arguments_rejected_without_device(lib):
                                  0, C.byref(res)) == ld.LD_EINVAL       # absolute eps only
     assert lib.mlmc_estimate_pdf(1e-3, C.byref(good), C.byref(q), 1, C.byref(prof), C.byref(o),
                                  5, C.byref(res)) == ld.LD_EINVAL       # unknown estimator
+    o_small = ld.estimate_opts(cfg)
+    o_small.d_workspace, o_small.workspace_bytes = fake.value, 4096    # refused before any use
+    assert lib.mlmc_estimate_pdf(1e-3, C.byref(good), C.byref(q), 1, C.byref(prof), C.byref(o_small),
+                                 0, C.byref(res)) == ld.LD_ENOMEM
 
 
 def test_adaptive_steps_validation_and_stability(lib):
