@@ -50,6 +50,18 @@ MUTANTS = [
     ("h_l off by one step", "double h = p->T / (double)M;               /* h_l = T / M_l */",
      "double h = p->T / (double)(M + 1);"),
     ("Y_l = P_l + P_{l-1}", "double y = pf - pc;", "double y = pf + pc;"),
+    ("Philox multipliers swapped",
+     "uint64_t prod0 = (uint64_t)0xD2511F53u * (uint64_t)x0;\n        uint64_t prod1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;",
+     "uint64_t prod0 = (uint64_t)0xCD9E8D57u * (uint64_t)x0;\n        uint64_t prod1 = (uint64_t)0xD2511F53u * (uint64_t)x2;"),
+    ("Philox nine rounds", "for (int round = 0; round < 10; ++round) {", "for (int round = 0; round < 9; ++round) {"),
+    ("Philox key bumped before round 0", "if (round > 0) {", "if (round >= 0) {"),
+    ("Philox output pairs swapped", "out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;",
+     "out[0] = x2; out[1] = x3; out[2] = x0; out[3] = x1;"),
+    ("Philox high halves not crossed", "uint32_t y0 = hi1 ^ x1 ^ k0;", "uint32_t y0 = hi0 ^ x1 ^ k0;"),
+    ("uniform u from the low word first", "double u = uniform_open(r[1], r[0]);",
+     "double u = uniform_open(r[0], r[1]);"),
+    ("counter without the level", "((uint32_t)level & 0xFFu) | (p->stream_id << 8)};",
+     "(p->stream_id << 8)};"),
     ("Box-Muller radius", "sqrt(-2.0 * log(u))", "sqrt(-log(u))"),
     ("Box-Muller pair both cosines", "out[1] = rho * sin(theta);", "out[1] = rho * cos(theta);"),
     ("Box-Muller angle pi v", "double theta = 2.0 * ORACLE_PI * v;", "double theta = ORACLE_PI * v;"),
@@ -72,7 +84,7 @@ MUTANTS = [
      "oracle_profile(p, 0.0, &su, &tau);\n            oracle_normals"),
 ]
 
-PIN_FILES = ["test_oracle_rng.py", "test_oracle_model.py", "test_oracle_closed_forms.py",
+PIN_FILES = ["test_oracle_rng.py", "test_oracle_philox_independent.py", "test_oracle_model.py", "test_oracle_closed_forms.py",
              "test_oracle_coupling.py", "test_oracle_smoothing_sums_driver.py",
              "test_oracle_paper_values.py", "test_oracle_adaptive.py"]
 

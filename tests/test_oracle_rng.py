@@ -1,10 +1,9 @@
 """Pins of the oracle's random numbers.
 
 The paper only says xi_n ~ N(0, 1) i.i.d. (Sec. 3.1). The oracle draws them with
-Philox4x32-10 and Box-Muller. Published known-answer vectors for Philox are not
-available offline, so the bit pattern itself is a convention shared with the GPU
-path (two independent implementations must agree bitwise); what the method needs -
-independent standard normals - is pinned here statistically.
+Philox4x32-10 and Box-Muller. The bit pattern is pinned by an independent numpy
+generator and two published known-answer vectors (test_oracle_philox_independent.py);
+what the method needs - independent standard normals - is pinned here statistically.
 """
 import numpy as np
 import pytest
