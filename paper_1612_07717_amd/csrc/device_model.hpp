@@ -299,7 +299,9 @@ __device__ __forceinline__ void fold(Path<R>& p, R H) {
 
 // expm1(-lambda h) of an O-step. SMALL: lambda_max h <= kSmallZ for this step size, so
 // the short series is exact to rounding for every X. The choice is made once per path
-// loop (it depends on the level and the step size only), never inside a step.
+// from that path's own step size (h for a fine path, 2h for a coarse one), never inside
+// a step and never from how the samples are laid out on the device: a sample's bits do
+// not depend on the block mode that runs it.
 template <typename R, bool SMALL>
 __device__ __forceinline__ R o_step_expm1(R z) {
     if (SMALL) return Math<R>::expm1_small(z);
@@ -396,34 +398,35 @@ __device__ __forceinline__ void init_path(const Consts<R>& c, Path<R>& p, R x0, 
 }
 
 // The time loop of one sample: M_l fine steps and, on levels >= 1, M_l / 2 coarse
-// steps driven by the combined fine noise. SMALL applies to both paths.
-template <typename R, int INTEG, int PROF, bool SMALL>
+// steps driven by the combined fine noise. SMALL_F and SMALL_C: o_step_expm1's choice for
+// the fine path (step h) and the coarse path (step 2h).
+template <typename R, int INTEG, int PROF, bool SMALL_F, bool SMALL_C>
 __device__ __forceinline__ void run_paths(const Consts<R>& c, const Stream& st, int level,
                                           uint32_t M, R h, R hh, R h2, Path<R>& f, Path<R>& g) {
     R tilde_a, tilde_b, w_a, w_b, z0, z1;
     if (level == 0) {
         for (uint32_t m = 0; m < M / 2; ++m) {
             Normals<R>::pair(philox(st, m), z0, z1);
-            step<R, INTEG, PROF, false, SMALL>(c, f, h, hh, z0, tilde_a, w_a);
-            step<R, INTEG, PROF, false, SMALL>(c, f, h, hh, z1, tilde_b, w_b);
+            step<R, INTEG, PROF, false, SMALL_F>(c, f, h, hh, z0, tilde_a, w_a);
+            step<R, INTEG, PROF, false, SMALL_F>(c, f, h, hh, z1, tilde_b, w_b);
         }
         if (M & 1u) {
             Normals<R>::pair(philox(st, M / 2), z0, z1);
-            step<R, INTEG, PROF, false, SMALL>(c, f, h, hh, z0, tilde_a, w_a);
+            step<R, INTEG, PROF, false, SMALL_F>(c, f, h, hh, z0, tilde_a, w_a);
         }
         return;
     }
     for (uint32_t m = 0; m < M / 2; ++m) {
         Normals<R>::pair(philox(st, m), z0, z1);
-        step<R, INTEG, PROF, false, SMALL>(c, f, h, hh, z0, tilde_a, w_a);   // fine step 2m
-        step<R, INTEG, PROF, false, SMALL>(c, f, h, hh, z1, tilde_b, w_b);   // fine step 2m+1
+        step<R, INTEG, PROF, false, SMALL_F>(c, f, h, hh, z0, tilde_a, w_a);   // fine step 2m
+        step<R, INTEG, PROF, false, SMALL_F>(c, f, h, hh, z1, tilde_b, w_b);   // fine step 2m+1
         R xi_c;
         if (INTEG == KINTEG_SE)
             xi_c = (tilde_a + tilde_b) * (R)0.70710678118654752440;  // Eq. (18)
         else
             xi_c = (w_a * tilde_a + tilde_b) * Math<R>::rsqrt(w_a * w_a + (R)1);   // Eq. (19)
         R unused_t, unused_w;
-        step<R, INTEG, PROF, true, SMALL>(c, g, h2, h, xi_c, unused_t, unused_w);
+        step<R, INTEG, PROF, true, SMALL_C>(c, g, h2, h, xi_c, unused_t, unused_w);
     }
 }
 
@@ -510,11 +513,16 @@ __device__ __forceinline__ void run_sample(const KProblem& kp, const Consts<R>& 
     const uint32_t M = (uint32_t)kp.M0 << level;                 // M_l = M_0 2^l
     const double hd = kp.T / (double)M;                           // h_l = T / M_l
     const R h = (R)hd, hh = (R)(0.5 * hd), h2 = (R)(2.0 * hd);
-    // the coarse step 2h decides on levels >= 1 (a short series there holds for h too)
-    if (small_steps<R>(kp, level == 0 ? hd : 2.0 * hd))
-        run_paths<R, INTEG, PROF, true>(c, st, level, M, h, hh, h2, f, g);
+    // each path by its own step: h for the fine path, 2h for the coarse one (a short
+    // series that holds for 2h holds for h too); symplectic Euler has no expm1
+    const bool sf = INTEG != KINTEG_SE && small_steps<R>(kp, hd);
+    const bool sc = INTEG != KINTEG_SE && level != 0 && small_steps<R>(kp, 2.0 * hd);
+    if (sc)
+        run_paths<R, INTEG, PROF, true, true>(c, st, level, M, h, hh, h2, f, g);
+    else if (sf)
+        run_paths<R, INTEG, PROF, true, false>(c, st, level, M, h, hh, h2, f, g);
     else
-        run_paths<R, INTEG, PROF, false>(c, st, level, M, h, hh, h2, f, g);
+        run_paths<R, INTEG, PROF, false, false>(c, st, level, M, h, hh, h2, f, g);
 }
 
 // Quantity of interest in FP64 (Sec. 2, Sec. 5).

@@ -14,6 +14,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <vector>
 
 #include "host_common.hpp"
@@ -104,6 +105,62 @@ void merge_into(HostSums& acc, const ld_level_sums& add) {
 // of whatever N_l end up drawn.
 constexpr int32_t kEarlyGap = 5;
 constexpr double kEarlyFraction = 1.0;
+
+// The second stream and the events of an estimate, kept for reuse instead of being made
+// and destroyed by every call. A kit belongs to one device and to one call at a time:
+// calls take a free kit of their device from the pool (or make one) and return it when
+// they end, so concurrent estimates never share a stream or an event. Kits live until
+// the process ends. The second stream has the default priority and does not synchronise
+// with the NULL stream by itself; every use orders it explicitly.
+struct EstimateKit {
+    int device = -1;
+    hipStream_t s2 = nullptr;                         // the early top-up's second stream
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;          // kernel time on the caller's stream
+    hipEvent_t e_start = nullptr;                     // the caller's stream before any launch
+    hipEvent_t e_long = nullptr, e_short0 = nullptr, e_short = nullptr;
+};
+
+std::mutex g_kit_mutex;
+std::vector<EstimateKit*> g_free_kits;
+
+// A free kit of `device` (the current device), or a new one; nullptr if the device
+// refuses a stream or an event.
+EstimateKit* acquire_kit(int device) {
+    {
+        std::lock_guard<std::mutex> lock(g_kit_mutex);
+        for (size_t i = 0; i < g_free_kits.size(); ++i) {
+            if (g_free_kits[i]->device == device) {
+                EstimateKit* k = g_free_kits[i];
+                g_free_kits.erase(g_free_kits.begin() + (long)i);
+                return k;
+            }
+        }
+    }
+    EstimateKit* k = new EstimateKit;
+    k->device = device;
+    bool ok = hipStreamCreateWithFlags(&k->s2, hipStreamNonBlocking) == hipSuccess;
+    for (hipEvent_t* e : {&k->ev0, &k->ev1, &k->e_start, &k->e_long, &k->e_short0, &k->e_short})
+        ok = ok && hipEventCreate(e) == hipSuccess;
+    if (!ok) {
+        for (hipEvent_t e : {k->ev0, k->ev1, k->e_start, k->e_long, k->e_short0, k->e_short})
+            if (e) (void)hipEventDestroy(e);
+        if (k->s2) (void)hipStreamDestroy(k->s2);
+        delete k;
+        return nullptr;
+    }
+    return k;
+}
+
+void release_kit(EstimateKit* k) {
+    if (k == nullptr) return;
+    std::lock_guard<std::mutex> lock(g_kit_mutex);
+    g_free_kits.push_back(k);
+}
+
+struct KitGuard {
+    EstimateKit* k;
+    ~KitGuard() { release_kit(k); }
+};
 
 struct Batch {
     ld_level_range r[LD_MAX_LEVELS];
@@ -264,8 +321,13 @@ int mlmc_estimate(double eps, const ld_qoi* qoi, ld_integrator integrator, const
     void* d_partials = (void*)(d_sums + LD_MAX_LEVELS);
     const size_t partial_bytes = ws_need - LD_MAX_LEVELS * sizeof(ld_level_sums);
 
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    const bool timing = hipEventCreate(&ev0) == hipSuccess && hipEventCreate(&ev1) == hipSuccess;
+    EstimateKit* kit = acquire_kit(device);
+    if (kit == nullptr) {
+        if (own_ws) (void)hipFree(ws);
+        return fail(LD_EDEVICE, "no stream or event for the estimate");
+    }
+    KitGuard kit_guard{kit};
+    hipEvent_t ev0 = kit->ev0, ev1 = kit->ev1;
 
     std::vector<HostSums> sums(LD_MAX_LEVELS);
     uint64_t drawn[LD_MAX_LEVELS] = {0};
@@ -296,41 +358,37 @@ int mlmc_estimate(double eps, const ld_qoi* qoi, ld_integrator integrator, const
         for (int32_t l = 0; l <= Ls; ++l) shortb.add(l, 0, opts.N_init);
         const size_t slots = partial_bytes / sizeof(ld_level_sums);
         const size_t off = longb.blocks();               // the second stream's partials follow
-        hipStream_t s2 = nullptr;
-        hipEvent_t e_long = nullptr, e_short0 = nullptr, e_short = nullptr;
+        hipStream_t s2 = kit->s2;
+        hipEvent_t e_long = kit->e_long, e_short0 = kit->e_short0, e_short = kit->e_short;
         if (off + shortb.blocks() > slots) {
             rc = fail(LD_ENOMEM, "early top-up: workspace too small for two batches");
         } else {
-            (void)hipEventCreate(&e_long);
             ld_level_sums* d_sums2 = d_sums + longb.n;
             void* d_part2 = (void*)((ld_level_sums*)d_partials + off);
             const size_t part2_bytes = partial_bytes - off * sizeof(ld_level_sums);
             ld_level_sums h_long[LD_MAX_LEVELS], h_short[LD_MAX_LEVELS], h_top[LD_MAX_LEVELS];
-            if (timing) (void)hipEventRecord(ev0, stream);
-            rc = run_batch(&prob, integrator, opts.precision, longb.r, longb.n, d_sums, d_partials,
-                           off * sizeof(ld_level_sums), nullptr, stream);
-            if (rc == LD_OK && e_long) (void)hipEventRecord(e_long, stream);
-            // the long levels run first; the second stream and its events are made meanwhile
-            if (rc == LD_OK && hipStreamCreateWithFlags(&s2, hipStreamNonBlocking) != hipSuccess) {
-                s2 = nullptr;
-                rc = fail(LD_EDEVICE, "early top-up: no second stream");
-            }
-            if (rc == LD_OK) {
-                (void)hipEventCreate(&e_short0);
-                (void)hipEventCreate(&e_short);
-            }
+            // the second stream starts after everything the caller queued before this call
+            // (its work may still use the workspace, e.g. memory a caching allocator
+            // handed out again)
+            if (hipEventRecord(kit->e_start, stream) != hipSuccess ||
+                hipStreamWaitEvent(s2, kit->e_start, 0) != hipSuccess)
+                rc = fail(LD_EDEVICE, "early top-up: cannot order the second stream");
+            if (rc == LD_OK) (void)hipEventRecord(ev0, stream);
+            if (rc == LD_OK)
+                rc = run_batch(&prob, integrator, opts.precision, longb.r, longb.n, d_sums, d_partials,
+                               off * sizeof(ld_level_sums), nullptr, stream);
+            if (rc == LD_OK) (void)hipEventRecord(e_long, stream);
             // kernel time of the second stream: each of its batches between two events
             double s2_seconds = 0.0;
             auto s2_span = [&]() {
                 float ms = 0.f;
-                if (e_short0 && e_short && hipEventElapsedTime(&ms, e_short0, e_short) == hipSuccess)
-                    s2_seconds += ms * 1e-3;
+                if (hipEventElapsedTime(&ms, e_short0, e_short) == hipSuccess) s2_seconds += ms * 1e-3;
             };
-            if (rc == LD_OK && e_short0) (void)hipEventRecord(e_short0, s2);
+            if (rc == LD_OK) (void)hipEventRecord(e_short0, s2);
             if (rc == LD_OK)
                 rc = run_batch(&prob, integrator, opts.precision, shortb.r, shortb.n, d_sums2, d_part2,
                                part2_bytes, nullptr, s2);
-            if (rc == LD_OK && e_short) (void)hipEventRecord(e_short, s2);
+            if (rc == LD_OK) (void)hipEventRecord(e_short, s2);
             if (rc == LD_OK &&
                 (hipMemcpyAsync(h_short, d_sums2, shortb.n * sizeof(ld_level_sums), hipMemcpyDeviceToHost, s2) !=
                      hipSuccess ||
@@ -361,10 +419,10 @@ int mlmc_estimate(double eps, const ld_qoi* qoi, ld_integrator integrator, const
                 if (po.status == 0 && !exceeds_budget(opts.max_fine_steps, opts.M0, drawn, dn_s, Ls))
                     for (int32_t l = 0; l <= Ls; ++l) topb.add(l, drawn[l], dn_s[l]);
                 if (topb.n > 0) {
-                    if (e_short0) (void)hipEventRecord(e_short0, s2);
+                    (void)hipEventRecord(e_short0, s2);
                     rc = run_batch(&prob, integrator, opts.precision, topb.r, topb.n, d_sums2, d_part2,
                                    part2_bytes, nullptr, s2);
-                    if (rc == LD_OK && e_short) (void)hipEventRecord(e_short, s2);
+                    if (rc == LD_OK) (void)hipEventRecord(e_short, s2);
                     if (rc == LD_OK &&
                         (hipMemcpyAsync(h_top, d_sums2, topb.n * sizeof(ld_level_sums), hipMemcpyDeviceToHost,
                                         s2) != hipSuccess ||
@@ -388,7 +446,7 @@ int mlmc_estimate(double eps, const ld_qoi* qoi, ld_integrator integrator, const
                     drawn[topb.r[j].level] += topb.r[j].n_samples;
                 }
                 out->launches += topb.n > 0 ? 3 : 2;
-                if (timing) {   // kernel time of both streams, summed as for one stream
+                {   // kernel time of both streams, summed as for one stream
                     float a = 0.f;
                     if (hipEventElapsedTime(&a, ev0, e_long) == hipSuccess) device_s += a * 1e-3;
                     device_s += s2_seconds;
@@ -398,12 +456,8 @@ int mlmc_estimate(double eps, const ld_qoi* qoi, ld_integrator integrator, const
         }
         if (rc != LD_OK) {   // work already queued may still use the workspace
             (void)hipStreamSynchronize(stream);
-            if (s2) (void)hipStreamSynchronize(s2);
+            (void)hipStreamSynchronize(s2);
         }
-        if (e_long) (void)hipEventDestroy(e_long);
-        if (e_short0) (void)hipEventDestroy(e_short0);
-        if (e_short) (void)hipEventDestroy(e_short);
-        if (s2) (void)hipStreamDestroy(s2);
     }
     for (;;) {
         if (rc != LD_OK) break;
@@ -418,18 +472,18 @@ int mlmc_estimate(double eps, const ld_qoi* qoi, ld_integrator integrator, const
             ++nr;
         }
         if (nr > 0) {
-            if (timing) (void)hipEventRecord(ev0, stream);
+            (void)hipEventRecord(ev0, stream);
             rc = run_batch(&prob, integrator, opts.precision, ranges, nr, d_sums, d_partials,
                            partial_bytes, nullptr, stream);
             if (rc != LD_OK) break;
-            if (timing) (void)hipEventRecord(ev1, stream);
+            (void)hipEventRecord(ev1, stream);
             if (hipMemcpyAsync(host_batch, d_sums, nr * sizeof(ld_level_sums), hipMemcpyDeviceToHost,
                                stream) != hipSuccess ||
                 hipStreamSynchronize(stream) != hipSuccess) {
                 rc = fail(LD_EDEVICE, std::string("level sums failed: ") + hipGetErrorString(hipGetLastError()));
                 break;
             }
-            if (timing) {
+            {
                 float ms = 0.f;
                 if (hipEventElapsedTime(&ms, ev0, ev1) == hipSuccess) device_s += ms * 1e-3;
             }
@@ -450,10 +504,6 @@ int mlmc_estimate(double eps, const ld_qoi* qoi, ld_integrator integrator, const
         if (exceeds_budget(opts.max_fine_steps, opts.M0, drawn, plan.dn, plan.L)) break;
         pin.L = plan.L;
         std::memcpy(dn, plan.dn, sizeof dn);
-    }
-    if (timing) {
-        (void)hipEventDestroy(ev0);
-        (void)hipEventDestroy(ev1);
     }
     if (own_ws) (void)hipFree(ws);
     if (rc != LD_OK) return rc;

@@ -240,7 +240,9 @@ __device__ __forceinline__ void pipe_samples(const KProblem& kp, const Consts<R>
     const uint32_t nch = (P + K - 1) / K;
     const double hd = kp.T / (double)M;
     const R h = (R)hd, hh = (R)(0.5 * hd), h2 = (R)(2.0 * hd);
-    const bool small_f = small_steps<R>(kp, hd), small_c = small_steps<R>(kp, 2.0 * hd);
+    // o_step_expm1's choice per path from its own step, as in run_sample (SE has no expm1)
+    const bool small_f = INTEG != KINTEG_SE && small_steps<R>(kp, hd);
+    const bool small_c = INTEG != KINTEG_SE && small_steps<R>(kp, 2.0 * hd);
     const Stream st = make_stream(kp.seed, kp.stream_id, level, item.sample_begin + local);
     Path<R> p;
     if (wave >= 2) {

@@ -73,3 +73,26 @@ def test_adaptive_problem_with_early_topup_equals_oracle():
     est = sum(s["sum_y"] / s["n"] for s in (oracle.level_sums(cfg, l, 0, n) for l, n in enumerate(g["N"])))
     say(f"  adaptive early top-up N={g['N']} {g['estimate']:.9f} oracle {est:.9f}")
     assert abs(g["estimate"] - est) <= 1e-11 * abs(est)
+
+
+def test_second_stream_waits_for_work_the_caller_queued_before():
+    """The workspace may be memory that work still queued on the caller's stream reads
+    (a caching allocator hands memory out again in stream order). Here a sum over the
+    workspace buffer is queued behind a long chain of matrix products; the estimate that
+    follows must not write the buffer before the sum has read it, on either of its two
+    streams. The sum sees the buffer's old contents and the estimate equals a run on a
+    fresh workspace bit for bit."""
+    import torch
+    ref = ld.estimate(1e-3, CFG, precision="fp32", early_topup=True, **KW)
+    nbytes = ld.estimate_workspace_bytes()
+    n = nbytes // 8
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    a = torch.randn(4096, 4096, device="cuda")
+    for _ in range(8):                       # some ms of queued work before the sum
+        a = (a @ a) * (1.0 / 64.0)
+    total = x.sum()
+    got = ld.estimate(1e-3, CFG, precision="fp32", early_topup=True, workspace=x.view(torch.uint8), **KW)
+    torch.cuda.synchronize()
+    say(f"  sum before the estimate {total.item():.0f} of {n}")
+    assert total.item() == float(n)
+    assert got["N"] == ref["N"] and got["estimate"] == ref["estimate"]

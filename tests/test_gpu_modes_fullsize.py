@@ -46,6 +46,37 @@ def test_pipe_and_stream_blocks_agree_bitwise(integ, prec):
     assert abs(s_pipe["sum_y"] - y.sum()) <= 1e-12 * np.abs(y).sum()
 
 
+def _lam_max(cfg):
+    """lambda = sigma_U / (kappa_tau X_c) is largest at the lower cut-off (Eqs. 5, 7)."""
+    e = cfg["eps_reg"]
+    su = cfg["kappa_sigma"] * cfg["u_star"] * (1.0 - e / cfg["H"]) ** 0.75
+    return su / (cfg["kappa_tau"] * e)
+
+
+# Levels where the short expm1 series holds for the fine step h but not for the coarse
+# step 2h (lambda_max h <= z_small < 2 lambda_max h; z_small = 1/16 in FP32, 1/64 in FP64):
+# there the two paths of a sample take different expm1 code, in either block mode.
+BOUNDARY = [("BAOAB", "fp32", 40, 5), ("GL", "fp32", 40, 5), ("BAOAB", "fp32", 8, 7), ("GL", "fp32", 8, 7),
+            ("BAOAB", "fp64", 40, 7), ("GL", "fp64", 40, 7), ("BAOAB", "fp64", 8, 9), ("GL", "fp64", 8, 9)]
+
+
+@pytest.mark.parametrize("integ,prec,M0,level", BOUNDARY)
+def test_pipe_and_stream_agree_on_the_short_series_boundary_level(integ, prec, M0, level):
+    cfg = W.neutral(500.0, integ, M0=M0)
+    h = cfg["T"] / (M0 << level)
+    z_small = 1.0 / 16 if prec == "fp32" else 1.0 / 64
+    lam = _lam_max(cfg)
+    assert lam * h <= z_small < 2.0 * lam * h
+    say(f"case boundary {integ} {prec} M0={M0} level={level}")
+    pipe = ld.level_samples(cfg, level, 3, PIPE_MAX, prec)        # PIPE blocks
+    stream = ld.level_samples(cfg, level, 3, PIPE_MAX + 1, prec)  # STREAM blocks
+    assert np.array_equal(pipe, stream[:PIPE_MAX])
+    if prec == "fp64":
+        ref = oracle.level_samples(cfg, level, 3, 48)
+        tol = 1e-12 * np.maximum(np.abs(ref), 1e-3 * cfg["H"])
+        assert np.all(np.abs(pipe[:48] - ref) <= tol)
+
+
 @pytest.mark.parametrize("H", [100.0, 400.0])
 @pytest.mark.parametrize("integ,prec", [("BAOAB", "fp32"), ("SE", "fp64"), ("GL", "fp64"), ("BAOAB", "fp64")])
 def test_pipe_and_stream_agree_when_steps_cross_the_layer(integ, prec, H):
