@@ -149,6 +149,22 @@ int mlmc_level_sums(const ld_problem* problem, ld_integrator integrator,
                     uint64_t n_samples, ld_level_sums* d_out, void* d_workspace,
                     size_t workspace_bytes, void* hip_stream);
 
+/* mlmc_level_sums without a workspace, for callers that cannot allocate device memory
+   (code under HIP graph capture, tight serving loops, harnesses that forbid allocation).
+   Same arguments, kernels and results (bit for bit) as mlmc_level_sums; the block
+   partials go to a device array the library owns instead: 32768 partials of 80 bytes
+   (2.5 MiB) per device, kept until the process ends, enough for any range (no launch of
+   one range uses more blocks). The call allocates nothing: no hipMalloc, hipFree or
+   allocating library routine; its first call on a device looks up the array's address
+   there. Calls on one device share that array, so calls that overlap on one device
+   (on different streams, or from several threads) race and give undefined results;
+   calls on one stream are ordered and safe. Nothing in the array needs clearing: every
+   launch writes each partial it reads. LD_ENOMEM if a range ever needed more partials
+   than the array holds; other errors as mlmc_level_sums. Asynchronous. */
+int mlmc_level_sums_noalloc(const ld_problem* problem, ld_integrator integrator,
+                            ld_precision precision, int32_t level, uint64_t sample_begin,
+                            uint64_t n_samples, ld_level_sums* d_out, void* hip_stream);
+
 /* Several (level, sample range) pairs of one problem in one launch; the most expensive
    levels are dispatched first. d_out: n_ranges ld_level_sums in device memory, in the
    order of `ranges`. 1 <= n_ranges <= LD_MAX_LEVELS. */

@@ -25,7 +25,8 @@ PROFILES = {"homogeneous": 0, "neutral": 1}
 RELEASES = {"fixed": 0, "gaussian": 1, "well_mixed": 2}
 QOIS = {"mean_z": 0, "p_above": 1, "p_box": 2, "velocity": 3, "velocity_sq": 4}
 
-EXPORTED = ["mlmc_level_sums_workspace", "mlmc_level_sums", "mlmc_level_sums_batch_workspace",
+EXPORTED = ["mlmc_level_sums_workspace", "mlmc_level_sums", "mlmc_level_sums_noalloc",
+            "mlmc_level_sums_batch_workspace",
             "mlmc_level_sums_batch", "mlmc_level_samples", "mlmc_plan",
             "mlmc_estimate_default_opts", "mlmc_estimate_workspace", "mlmc_estimate",
             "ld_engine_default_opts", "ld_engine_create", "ld_engine_destroy", "ld_engine_submit",
@@ -206,6 +207,8 @@ def load():
     lib.mlmc_level_sums_workspace.restype = C.c_size_t
     lib.mlmc_level_sums.argtypes = [P(Problem), C.c_int, C.c_int, C.c_int32, C.c_uint64,
                                     C.c_uint64, V, V, C.c_size_t, V]
+    lib.mlmc_level_sums_noalloc.argtypes = [P(Problem), C.c_int, C.c_int, C.c_int32, C.c_uint64,
+                                            C.c_uint64, V, V]
     lib.mlmc_level_sums_batch_workspace.argtypes = [P(LevelRange), C.c_int32]
     lib.mlmc_level_sums_batch_workspace.restype = C.c_size_t
     lib.mlmc_level_sums_batch.argtypes = [P(Problem), C.c_int, C.c_int, P(LevelRange),
@@ -333,6 +336,24 @@ def level_sums(cfg, level, begin, n, precision="fp64", stream=None) -> dict:
     out = torch.zeros(C.sizeof(LevelSums), dtype=torch.uint8, device="cuda")
     ws = torch.empty(max(level_sums_workspace(n), 1), dtype=torch.uint8, device="cuda")
     level_sums_async(cfg, level, begin, n, out, ws, precision, stream)
+    torch.cuda.synchronize()
+    return _sums_from_tensor(out)
+
+
+def level_sums_noalloc_async(cfg, level, begin, n, out, precision="fp64", stream=None):
+    """Enqueue mlmc_level_sums_noalloc into the CUDA tensor `out` (>= 80 bytes): no
+    workspace, the library's own partials array. Does not synchronise."""
+    lib = load()
+    p = make_problem(cfg)
+    _check(lib.mlmc_level_sums_noalloc(C.byref(p), INTEGRATORS[cfg["integrator"]], PRECISIONS[precision],
+                                       int(level), int(begin), int(n), C.c_void_p(out.data_ptr()),
+                                       _stream_handle(stream)))
+
+
+def level_sums_noalloc(cfg, level, begin, n, precision="fp64", stream=None) -> dict:
+    torch = _torch()
+    out = torch.zeros(C.sizeof(LevelSums), dtype=torch.uint8, device="cuda")
+    level_sums_noalloc_async(cfg, level, begin, n, out, precision, stream)
     torch.cuda.synchronize()
     return _sums_from_tensor(out)
 

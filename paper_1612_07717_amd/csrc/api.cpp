@@ -263,6 +263,30 @@ int mlmc_level_sums(const ld_problem* problem, ld_integrator integrator, ld_prec
                      nullptr, hip_stream);
 }
 
+int mlmc_level_sums_noalloc(const ld_problem* problem, ld_integrator integrator,
+                            ld_precision precision, int32_t level, uint64_t sample_begin,
+                            uint64_t n_samples, ld_level_sums* d_out, void* hip_stream) {
+    ld_level_range r;
+    std::memset(&r, 0, sizeof r);
+    r.level = level;
+    r.sample_begin = sample_begin;
+    r.n_samples = n_samples;
+    KArgs args;
+    uint32_t total = 0;
+    int rc = build_batch(problem, integrator, precision, &r, 1, &args, &total);
+    if (rc != LD_OK) return rc;
+    if (d_out == nullptr) return fail(LD_EINVAL, "d_out is NULL");
+    if (total > kScratchPartials)
+        return fail(LD_ENOMEM, "range needs " + std::to_string(total) + " block partials; the "
+                    "library's own array holds " + std::to_string(kScratchPartials));
+    ld_level_sums* d_scratch = nullptr;
+    rc = scratch_partials(&d_scratch);
+    if (rc != LD_OK) return fail(rc, "no device address for the library's partials array");
+    rc = launch_levels(args, total, d_scratch, d_out, nullptr, hip_stream);
+    if (rc != LD_OK) return fail(rc, std::string("kernel launch failed: ") + hipGetErrorString(hipGetLastError()));
+    return LD_OK;
+}
+
 size_t mlmc_level_sums_batch_workspace(const ld_level_range* ranges, int32_t n_ranges) {
     if (ranges == nullptr || n_ranges < 1) return 0;
     size_t total = 0;

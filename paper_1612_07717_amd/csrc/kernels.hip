@@ -8,6 +8,8 @@
 // item's partials in a fixed order. No atomics: results are bitwise reproducible.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "device_model.hpp"
 #include "ld_internal.hpp"
 
@@ -743,6 +745,28 @@ int launch_pdf_bins(const KBins& bins, const KProblem& kp, const double* d_dump,
     hipLaunchKernelGGL(pdf_merge_kernel, dim3(bins.n_bins), dim3(kBlock), 0, s, d_partials, nb, bins.n_bins,
                        d_out);
     return hipGetLastError() == hipSuccess ? LD_OK : LD_EDEVICE;
+}
+
+// Partials of mlmc_level_sums_noalloc. In host code `scratch` names a host-side
+// stand-in, not device memory: kernels get the address that scratch_partials looks up.
+static __device__ __align__(256) ld_level_sums scratch[kScratchPartials];
+
+constexpr int kMaxDevices = 64;
+
+int scratch_partials(ld_level_sums** out) {
+    static std::mutex mu;
+    static ld_level_sums* addr[kMaxDevices] = {};
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0) return LD_ENODEVICE;
+    if (dev >= kMaxDevices) return LD_EDEVICE;
+    std::lock_guard<std::mutex> lock(mu);
+    if (addr[dev] == nullptr) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return LD_EDEVICE;
+        addr[dev] = (ld_level_sums*)p;
+    }
+    *out = addr[dev];
+    return LD_OK;
 }
 
 using LevelKernel = void (*)(const KArgs, ld_level_sums*, double*);

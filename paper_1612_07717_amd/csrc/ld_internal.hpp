@@ -70,6 +70,15 @@ struct KArgs {
 int launch_levels(const KArgs& args, uint32_t total_blocks, ld_level_sums* d_partials,
                   ld_level_sums* d_out, double* d_dump, void* stream);
 
+// Block partials of the allocation-free level sums: a device array the library owns,
+// one per device for the life of the process. No launch plan of one (level, range) uses
+// more blocks than this (STREAM ranges are cut into at most 32768 blocks, PIPE ranges
+// into at most 2048, adaptive ones into at most 1280).
+constexpr uint32_t kScratchPartials = 32768;
+// Device address of that array on the current device (looked up once per device).
+// LD_ENODEVICE without a device, LD_EDEVICE if the runtime refuses the lookup.
+int scratch_partials(ld_level_sums** out);
+
 // ---- multi-estimator engine ------------------------------------------------------
 // A tile is one block's work: block `local_block` of the range (slot, level,
 // sample_begin, n_samples) in the given mode.

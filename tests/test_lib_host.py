@@ -315,3 +315,17 @@ def test_device_code_flags_fix_the_rounding():
     assert not any(x.startswith("-ffast-math") or x == "-ffp-contract=fast" for x in f)
     i = f.index("-packed-fp32-ops")
     assert f[i - 1] == "-Xclang" and f[i - 2] == "-target-feature" and f[i - 3] == "-Xclang"
+
+
+def test_noalloc_level_sums_validates_before_device_use(lib):
+    """mlmc_level_sums_noalloc takes no workspace; its arguments are checked as
+    mlmc_level_sums checks them, before any device call."""
+    good = W.neutral(300.0, "GL")
+    fake = C.c_void_p(0x1000)   # never dereferenced: validation fails first
+    for cfg, level in ((dict(good, H=-1.0), 0), (dict(good, M0=0), 0), (good, 32),
+                       (dict(good, M0=1 << 20), 12)):
+        p = ld.make_problem(cfg)
+        assert lib.mlmc_level_sums_noalloc(C.byref(p), 1, 0, level, 0, 100, fake, None) == ld.LD_EINVAL
+    p = ld.make_problem(good)
+    assert lib.mlmc_level_sums_noalloc(C.byref(p), 7, 0, 0, 0, 100, fake, None) == ld.LD_EINVAL
+    assert lib.mlmc_level_sums_noalloc(C.byref(p), 1, 0, 0, 0, 100, None, None) == ld.LD_EINVAL
