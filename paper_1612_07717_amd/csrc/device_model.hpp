@@ -297,6 +297,43 @@ __device__ __forceinline__ void fold(Path<R>& p, R H) {
 }
 
 
+// How a step treats its position updates. FOLD_EXACT folds each one (fold()).
+// FOLD_TRACK leaves them unfolded and only records, in `key`, the largest fold key
+// (FoldKey) of the positions reached: for positions in [0, H] fold() changes nothing,
+// so while every key stays within FoldKey::limit(H) the tracked steps are the exact
+// steps bit for bit, and otherwise the caller repeats them with FOLD_EXACT.
+enum { FOLD_EXACT = 0, FOLD_TRACK = 1 };
+
+// A position's fold key: an unsigned number that exceeds limit(H) for every position
+// outside [0, H], for -0 and for NaN. FP32: the bit pattern itself (non-negative
+// floats order as their patterns; a sign bit makes the pattern larger than any positive
+// one). FP64: the high 32 bits, against hi(H) - 1, which also flags the positions in the
+// last 2^-20 of H below it (repeated, not wrongly kept).
+template <typename R>
+struct FoldKey;
+
+template <>
+struct FoldKey<float> {
+    static __device__ __forceinline__ uint32_t key(float x) { return __float_as_uint(x); }
+    static __device__ __forceinline__ uint32_t limit(float H) { return __float_as_uint(H); }
+};
+
+template <>
+struct FoldKey<double> {
+    static __device__ __forceinline__ uint32_t key(double x) { return (uint32_t)__double2hiint(x); }
+    static __device__ __forceinline__ uint32_t limit(double H) { return (uint32_t)__double2hiint(H) - 1u; }
+};
+
+template <typename R, int FOLD>
+__device__ __forceinline__ void fold_or_track(Path<R>& p, R H, uint32_t& key) {
+    if (FOLD == FOLD_EXACT) {
+        fold(p, H);
+    } else {
+        const uint32_t k = FoldKey<R>::key(p.x);
+        key = key > k ? key : k;
+    }
+}
+
 // expm1(-lambda h) of an O-step. SMALL: lambda_max h <= kSmallZ for this step size, so
 // the short series is exact to rounding for every X. The choice is made once per path
 // from that path's own step size (h for a fine path, 2h for a coarse one), never inside
@@ -317,9 +354,9 @@ __device__ __forceinline__ bool small_steps(const KProblem& kp, double h) {
 // One step of size h. COARSE: xi is the combined extended noise and the physical noise
 // is S xi; otherwise xi is the physical noise and `tilde` receives S xi. `w` receives
 // e^{-lambda h} of the O-step (GL, BAOAB). SMALL: see o_step_expm1.
-template <typename R, int INTEG, int PROF, bool COARSE, bool SMALL>
-__device__ __forceinline__ void step(const Consts<R>& c, Path<R>& p, R h, R hh, R xi,
-                                     R& tilde, R& w) {
+template <typename R, int INTEG, int PROF, bool COARSE, bool SMALL, int FOLD>
+__device__ __forceinline__ void step_impl(const Consts<R>& c, Path<R>& p, R h, R hh, R xi,
+                                          R& tilde, R& w, uint32_t& key) {
     if (INTEG == KINTEG_SE) {                                        // Eq. (8)
         R su, z, a, b;                                               // z = -lambda h
         coeffs_at<R, PROF>(c, p.x, h, su, z, a, b);
@@ -329,7 +366,7 @@ __device__ __forceinline__ void step(const Consts<R>& c, Path<R>& p, R h, R hh, 
         const R drift = -(a + b * p.u * p.u);
         p.u = ((R)1 + z) * p.u + drift * h + amp * noise;
         p.x = p.x + p.u * h;
-        fold(p, c.H);
+        fold_or_track<R, FOLD>(p, c.H, key);
         w = (R)1;
     } else if (INTEG == KINTEG_GL) {                                 // Eq. (9)
         R su, z, a, b;
@@ -342,11 +379,11 @@ __device__ __forceinline__ void step(const Consts<R>& c, Path<R>& p, R h, R hh, 
         const R us = w * p.u + amp * noise;                          // O
         p.u = us - (a + b * us * us) * h;                            // B at (X_n, U*)
         p.x = p.x + p.u * h;                                         // A
-        fold(p, c.H);
+        fold_or_track<R, FOLD>(p, c.H, key);
     } else {                                                         // Eq. (10)
         p.u = p.u - (p.a + p.b * p.u * p.u) * hh;                    // B at (X_n, U_n)
         p.x = p.x + p.u * hh;                                        // A
-        fold(p, c.H);
+        fold_or_track<R, FOLD>(p, c.H, key);
         R su, z;
         o_coeffs<R, PROF>(c, p.x, h, su, z);
         const R noise = COARSE ? Math<R>::flip(xi, p.sgn) : xi;
@@ -356,10 +393,18 @@ __device__ __forceinline__ void step(const Consts<R>& c, Path<R>& p, R h, R hh, 
         const R amp = su * Math<R>::sqrt_(-e1 * ((R)2 + e1));
         p.u = w * p.u + amp * noise;                                 // O at X_{n+1/2}
         p.x = p.x + p.u * hh;                                        // A
-        fold(p, c.H);
+        fold_or_track<R, FOLD>(p, c.H, key);
         drift_at<R, PROF>(c, p.x, p.a, p.b);
         p.u = p.u - (p.a + p.b * p.u * p.u) * hh;                    // B at (X_{n+1}, U*)
     }
+}
+
+// One step with every position update folded (Eq. 6, Sec. 4).
+template <typename R, int INTEG, int PROF, bool COARSE, bool SMALL>
+__device__ __forceinline__ void step(const Consts<R>& c, Path<R>& p, R h, R hh, R xi,
+                                     R& tilde, R& w) {
+    uint32_t unused = 0;
+    step_impl<R, INTEG, PROF, COARSE, SMALL, FOLD_EXACT>(c, p, h, hh, xi, tilde, w, unused);
 }
 
 // Initial state shared by both paths of a sample.

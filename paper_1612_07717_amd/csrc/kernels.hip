@@ -186,19 +186,40 @@ struct PipeLds {
 
 // Fine wave of a wave-specialised block: K fine step pairs of one chunk (fine steps
 // 2m, 2m + 1 for m = m0 .. m0 + K - 1 below P), reading the normals of buffer b and
-// publishing S xi of both steps and w of the first for the coarse wave.
+// publishing S xi of both steps and w of the first for the coarse wave. The chunk runs
+// first without folds, tracking how far its positions went (FOLD_TRACK): a path stays
+// in [0, H] on almost every chunk, and then no position test or branch sits on the
+// chain of its steps. A lane whose positions left [0, H] repeats the chunk from its
+// saved state with folded steps and publishes again, so every lane ends with the
+// folded steps' results bit for bit.
 template <typename R, int INTEG, int PROF, bool SMALL>
 __device__ __forceinline__ void pipe_fine_chunk(const Consts<R>& c, Path<R>& p, R h, R hh,
                                                 PipeLds<R>& L, uint32_t b, uint32_t m0,
                                                 uint32_t P, int lane) {
+    const Path<R> p0 = p;
+    uint32_t key = 0;
     for (int j = 0; j < kPipeChunk; ++j) {
         if (m0 + j < P) {
             R ta, tb, wa, wb;
-            step<R, INTEG, PROF, false, SMALL>(c, p, h, hh, L.nrm[b][j][0][lane], ta, wa);
-            step<R, INTEG, PROF, false, SMALL>(c, p, h, hh, L.nrm[b][j][1][lane], tb, wb);
+            step_impl<R, INTEG, PROF, false, SMALL, FOLD_TRACK>(c, p, h, hh, L.nrm[b][j][0][lane], ta, wa, key);
+            step_impl<R, INTEG, PROF, false, SMALL, FOLD_TRACK>(c, p, h, hh, L.nrm[b][j][1][lane], tb, wb, key);
             L.msg[b][j][0][lane] = ta;
             L.msg[b][j][1][lane] = tb;
             L.msg[b][j][2][lane] = wa;
+        }
+    }
+    if (__builtin_expect(key > FoldKey<R>::limit(c.H), 0)) {
+        p = p0;
+#pragma unroll 1
+        for (int j = 0; j < kPipeChunk; ++j) {
+            if (m0 + j < P) {
+                R ta, tb, wa, wb;
+                step<R, INTEG, PROF, false, SMALL>(c, p, h, hh, L.nrm[b][j][0][lane], ta, wa);
+                step<R, INTEG, PROF, false, SMALL>(c, p, h, hh, L.nrm[b][j][1][lane], tb, wb);
+                L.msg[b][j][0][lane] = ta;
+                L.msg[b][j][1][lane] = tb;
+                L.msg[b][j][2][lane] = wa;
+            }
         }
     }
 }
