@@ -47,6 +47,7 @@ struct Math<float> {
     }
     static __device__ __forceinline__ float quot(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
     static __device__ __forceinline__ float floor_(float x) { return __builtin_floorf(x); }
+    static __device__ __forceinline__ float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
     // v_med3_f32: the median of (x, lo, hi) is x clamped to [lo, hi] for lo <= hi
     static __device__ __forceinline__ float clamp_(float x, float lo, float hi) {
         return __builtin_amdgcn_fmed3f(x, lo, hi);
@@ -130,6 +131,7 @@ struct Math<double> {
     }
     static __device__ __forceinline__ double quot(double a, double b) { return a / b; }
     static __device__ __forceinline__ double floor_(double x) { return floor(x); }
+    static __device__ __forceinline__ double fma_(double a, double b, double c) { return fma(a, b, c); }
     // expm1 by argument reduction z = k ln2 + r, |r| <= ln2/2 (Cody & Waite: ln2 in two
     // parts, the first with 31 significant bits so that k ln2_hi is exact), the Taylor
     // series of expm1(r) to degree 13 (truncation below 2e-17 relative), and
@@ -245,33 +247,43 @@ __device__ __forceinline__ void coeffs_at(const Consts<R>& c, R x, R h, R& su, R
         const R r = Math<R>::sqrt_(d * sqd);
         su = c.ksH * r;
         z = r * ((-c.kl * h) * Math<R>::rcp(xc));
-        const bool inside = (x >= c.eps) && (x <= c.Hme);   // then xc == x
+        // inside [eps_reg, H - eps_reg] exactly when the cut-off leaves X as it is (one
+        // vector compare; no scalar combination of two)
+        const bool inside = xc == x;
         a = inside ? c.acoef_h * sqd : (R)0;
         b = inside ? (R)0.75 * invd : (R)0;
     }
 }
 
-// a = (3/4)(kappa_sigma u_*)^2 sqrt(H - X) / H^(3/2), b = (3/4) / (H - X) inside
-// [eps_reg, H - eps_reg], 0 outside.
+// The drift coefficients of a B half-step of length hh at X: a hh and b hh, with
+// a = (3/4)(kappa_sigma u_*)^2 sqrt(H - X) / H^(3/2) and b = (3/4) / (H - X) inside
+// [eps_reg, H - eps_reg], 0 outside. The half-step is then U - a hh - (b hh) U^2.
 template <typename R, int PROF>
-__device__ __forceinline__ void drift_at(const Consts<R>& c, R x, R& a, R& b) {
+__device__ __forceinline__ void drift_at(const Consts<R>& c, R x, R hh, R& ah, R& bh) {
     if (PROF == KPROFILE_HOMOGENEOUS) {
-        a = (R)0;
-        b = (R)0;
+        ah = (R)0;
+        bh = (R)0;
     } else {
-        const bool inside = (x >= c.eps) && (x <= c.Hme);
+        const bool inside = Math<R>::clamp_(x, c.eps, c.Hme) == x;
         R sq, inv;
         Math<R>::sqrt_and_rcp(c.H - x, sq, inv);
-        a = inside ? c.acoef_h * sq : (R)0;
-        b = inside ? (R)0.75 * inv : (R)0;
+        ah = inside ? (c.acoef_h * hh) * sq : (R)0;
+        bh = inside ? ((R)0.75 * hh) * inv : (R)0;
     }
+}
+
+// U - a' - b' U^2 (a B half-step with a' = a hh, b' = b hh): b' U and U - a' are
+// independent, so two operations follow U.
+template <typename R>
+__device__ __forceinline__ R kick(R u, R ah, R bh) {
+    return (u - ah) - (bh * u) * u;
 }
 
 template <typename R>
 struct Path {
     R x, u;
     uint32_t sgn;   // reflection sign S as a sign-bit mask (0: S = +1)
-    R a, b;         // drift coefficients at x (BAOAB carries them to the next step)
+    R a, b;         // BAOAB: a hh and b hh of drift_at at x, carried to the next step
     bool bad;       // ran away (more than kFoldMax reflections): non-finite
 };
 
@@ -375,13 +387,13 @@ __device__ __forceinline__ void step_impl(const Consts<R>& c, Path<R>& p, R h, R
         if (!COARSE) tilde = Math<R>::flip(xi, p.sgn);
         const R e1 = o_step_expm1<R, SMALL>(z);
         w = (R)1 + e1;
-        const R amp = su * Math<R>::sqrt_(-e1 * ((R)2 + e1));
-        const R us = w * p.u + amp * noise;                          // O
-        p.u = us - (a + b * us * us) * h;                            // B at (X_n, U*)
+        const R sn = su * noise;
+        const R us = Math<R>::fma_(sn, Math<R>::sqrt_(-e1 * ((R)2 + e1)), w * p.u);   // O
+        p.u = kick(us, a * h, b * h);                                // B at (X_n, U*)
         p.x = p.x + p.u * h;                                         // A
         fold_or_track<R, FOLD>(p, c.H, key);
     } else {                                                         // Eq. (10)
-        p.u = p.u - (p.a + p.b * p.u * p.u) * hh;                    // B at (X_n, U_n)
+        p.u = kick(p.u, p.a, p.b);                                   // B at (X_n, U_n)
         p.x = p.x + p.u * hh;                                        // A
         fold_or_track<R, FOLD>(p, c.H, key);
         R su, z;
@@ -390,12 +402,12 @@ __device__ __forceinline__ void step_impl(const Consts<R>& c, Path<R>& p, R h, R
         if (!COARSE) tilde = Math<R>::flip(xi, p.sgn);
         const R e1 = o_step_expm1<R, SMALL>(z);
         w = (R)1 + e1;
-        const R amp = su * Math<R>::sqrt_(-e1 * ((R)2 + e1));
-        p.u = w * p.u + amp * noise;                                 // O at X_{n+1/2}
+        const R sn = su * noise;
+        p.u = Math<R>::fma_(sn, Math<R>::sqrt_(-e1 * ((R)2 + e1)), w * p.u);   // O at X_{n+1/2}
         p.x = p.x + p.u * hh;                                        // A
         fold_or_track<R, FOLD>(p, c.H, key);
-        drift_at<R, PROF>(c, p.x, p.a, p.b);
-        p.u = p.u - (p.a + p.b * p.u * p.u) * hh;                    // B at (X_{n+1}, U*)
+        drift_at<R, PROF>(c, p.x, hh, p.a, p.b);
+        p.u = kick(p.u, p.a, p.b);                                   // B at (X_{n+1}, U*)
     }
 }
 
@@ -431,15 +443,16 @@ __device__ __forceinline__ void initial_state(const KProblem& kp, const Consts<R
     u0 = sigma_at<R, PROF>(c, x0) * z0;
 }
 
+// hh: the path's B half-step (h/2 for a fine path, h for a coarse one); BAOAB only.
 template <typename R, int INTEG, int PROF>
-__device__ __forceinline__ void init_path(const Consts<R>& c, Path<R>& p, R x0, R u0) {
+__device__ __forceinline__ void init_path(const Consts<R>& c, Path<R>& p, R x0, R u0, R hh) {
     p.x = x0;
     p.u = u0;
     p.sgn = 0u;
     p.bad = false;
     p.a = (R)0;
     p.b = (R)0;
-    if (INTEG == KINTEG_BAOAB) drift_at<R, PROF>(c, x0, p.a, p.b);
+    if (INTEG == KINTEG_BAOAB) drift_at<R, PROF>(c, x0, hh, p.a, p.b);
 }
 
 // The time loop of one sample: M_l fine steps and, on levels >= 1, M_l / 2 coarse
@@ -553,11 +566,11 @@ __device__ __forceinline__ void run_sample(const KProblem& kp, const Consts<R>& 
     const Stream st = make_stream(kp.seed, kp.stream_id, level, sample);
     R x0, u0;
     initial_state<R, PROF>(kp, c, st, x0, u0);
-    init_path<R, INTEG, PROF>(c, f, x0, u0);
-    init_path<R, INTEG, PROF>(c, g, x0, u0);
     const uint32_t M = (uint32_t)kp.M0 << level;                 // M_l = M_0 2^l
     const double hd = kp.T / (double)M;                           // h_l = T / M_l
     const R h = (R)hd, hh = (R)(0.5 * hd), h2 = (R)(2.0 * hd);
+    init_path<R, INTEG, PROF>(c, f, x0, u0, hh);
+    init_path<R, INTEG, PROF>(c, g, x0, u0, h);
     // each path by its own step: h for the fine path, 2h for the coarse one (a short
     // series that holds for 2h holds for h too); symplectic Euler has no expm1
     const bool sf = INTEG != KINTEG_SE && small_steps<R>(kp, hd);

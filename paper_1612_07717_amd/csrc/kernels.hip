@@ -271,7 +271,7 @@ __device__ __forceinline__ void pipe_samples(const KProblem& kp, const Consts<R>
     if (wave >= 2) {
         R x0, u0;
         initial_state<R, PROF>(kp, c, st, x0, u0);
-        init_path<R, INTEG, PROF>(c, p, x0, u0);
+        init_path<R, INTEG, PROF>(c, p, x0, u0, wave == 2 ? hh : h);   // fine or coarse B half-step
     }
     for (uint32_t s = 0; s < nch + 2; ++s) {
         if (wave < 2) {
@@ -396,8 +396,8 @@ __device__ __forceinline__ void adaptive_lane(const KProblem& kp, const Consts<R
             st = make_stream(kp.seed, kp.stream_id, level, item.sample_begin + cur);
             R x0, u0;
             initial_state<R, PROF>(kp, c, st, x0, u0);
-            init_path<R, KINTEG_SE, PROF>(c, f, x0, u0);
-            init_path<R, KINTEG_SE, PROF>(c, g, x0, u0);
+            init_path<R, KINTEG_SE, PROF>(c, f, x0, u0, (R)0);
+            init_path<R, KINTEG_SE, PROF>(c, g, x0, u0, (R)0);
             kf = acoef_at<R, PROF>(c, x0);
             kg = kf;
             tf = tc = tau = 0;
