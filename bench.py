@@ -30,21 +30,32 @@ sys.path.insert(0, ROOT)
 import workloads as W  # noqa: E402
 
 # Peak figures of one MI355X (public): 256 CUs at 2.4 GHz. FP32 vector 157.3 TFLOP/s
-# (packed FMA: 256 FLOP/clk/CU); FP64 vector 78.6 TFLOP/s (128 FLOP/clk/CU).
+# counts packed FMA (two FP32 FMAs per lane per clock), which this build never emits;
+# without packing the FP32 vector peak is that of FP64, 78.6 TFLOP/s (one FMA per lane
+# per clock: 256 CUs x 64 lanes x 2 FLOP x 2.4 GHz).
 PEAK_TFLOPS = {"fp32": 157.3, "fp64": 78.6}
+PEAK_TFLOPS_UNPACKED = {"fp32": 78.6, "fp64": 78.6}
 
-# Arithmetic operations the method performs per coupled fine step (one fine step, half
-# a coarse step, half a coupling, half a Philox block, one normal), counted from the
-# equations: +, -, *, compare, min/max, select and integer ops count 1, a multiply-add
-# counts 2, each elementary function (sqrt, reciprocal, expm1, log, sin, cos) counts 1.
-# Breakdown in DESIGN.md ("Algorithmic work per coupled step").
-OPS_PER_COUPLED_STEP = {
-    ("BAOAB", "neutral"): 135.5, ("GL", "neutral"): 119.0, ("SE", "neutral"): 115.5,
-    ("BAOAB", "homogeneous"): 91.0, ("GL", "homogeneous"): 84.5, ("SE", "homogeneous"): 83.5,
-}
+# Operations the method performs per coupled fine step (one fine step, half a coarse
+# step, half a coupling, one normal and half a Philox block), counted from the
+# equations: floating-point ALU operations (add, multiply, multiply-add, compare,
+# min/max, select; each counts one) plus elementary functions (square root,
+# reciprocal, exp/expm1, log, sine/cosine; one each), and apart from them the integer
+# operations of the generator. BAOAB: 70 + 13 and 25; symplectic Euler and geometric
+# Langevin: 50 + 10 and 25. Breakdown in DESIGN.md ("Algorithmic work per coupled step").
+FP_OPS_PER_COUPLED_STEP = {"BAOAB": 83.0, "GL": 60.0, "SE": 60.0}
+INT_OPS_PER_COUPLED_STEP = 25.0
 
-# The dominant kernel: the FP32 BAOAB level kernel of the neutral profile.
-DOMINANT_KERNEL = "_ZN3ldm12level_kernelIfLi2ELi1EEEvNS_5KArgsEP13ld_level_sumsPd"
+INTEGRATOR_INDEX = {"SE": 0, "GL": 1, "BAOAB": 2}
+
+
+def dominant_kernel(precision: str = "fp32", integrator: str = "BAOAB") -> str:
+    """Symbol of the level kernel of the neutral profile that runs the estimate."""
+    t = "f" if precision == "fp32" else "d"
+    return f"_ZN3ldm12level_kernelI{t}Li{INTEGRATOR_INDEX[integrator]}ELi1EEEvNS_5KArgsEP13ld_level_sumsPd"
+
+
+DOMINANT_KERNEL = dominant_kernel()
 
 
 def _elf_sections(blob: bytes, base: int = 0):
@@ -95,76 +106,108 @@ def kernel_hash(symbol: str = DOMINANT_KERNEL) -> str:
     return "missing"
 
 
-def hbm_traffic(precision: str):
+def hbm_traffic(precision: str, integrator: str = "BAOAB"):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or None when
-    the summary is missing or the kernel sources changed since it was taken."""
+    the summary is missing or the kernel's machine code changed since it was taken."""
     path = os.path.join(ROOT, "profiles", f"level_kernel_{precision}_single_large_traffic.json")
     try:
         with open(path) as f:
             d = json.load(f)
     except OSError:
         return None
-    if d.get("kernel_hash") != kernel_hash():
+    if d.get("kernel_hash") != kernel_hash(dominant_kernel(precision, integrator)):
         return None
     return d.get("bytes_per_launch")
 
 
-def valu_issue(precision: str):
+def valu_issue(precision: str, integrator: str = "BAOAB"):
     """Measured VALU issue utilisation of the dominant kernel's launches (committed
-    rocprofv3 counter summary), or None when missing or taken on other kernel sources."""
+    rocprofv3 counter summary), or None when missing or taken on other machine code."""
     path = os.path.join(ROOT, "profiles", f"level_kernel_{precision}_single_large_valu.json")
     try:
         with open(path) as f:
             d = json.load(f)
     except OSError:
         return None
-    if d.get("kernel_hash") != kernel_hash():
+    if d.get("kernel_hash") != kernel_hash(dominant_kernel(precision, integrator)):
         return None
     return {f"{r['blocks']}_blocks": round(r["issue_frac"], 3) for r in d["launches"] if r.get("issue_frac")}
 
 
+def roofline(precision: str, integrator: str, fine_steps: float, kernel_seconds: float,
+             launches: int) -> dict:
+    """ALU roofline of the level kernel over the timed estimates: the algorithmic
+    floating-point operations (FP_OPS_PER_COUPLED_STEP per coupled fine step) over the
+    kernel time measured with HIP events on the launch streams (summed over launches),
+    against the published vector peak and the peak without packed FP32."""
+    fp = FP_OPS_PER_COUPLED_STEP[integrator]
+    achieved = fp * fine_steps / kernel_seconds / 1e12
+    peak, unpacked = PEAK_TFLOPS[precision], PEAK_TFLOPS_UNPACKED[precision]
+    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": hbm_traffic(precision, integrator),
+            "kernel": f"level_kernel<{'float' if precision == 'fp32' else 'double'}, {integrator}, neutral>",
+            "fp_ops_per_coupled_step": fp, "int_ops_per_coupled_step": INT_OPS_PER_COUPLED_STEP,
+            "int_tops": INT_OPS_PER_COUPLED_STEP * fine_steps / kernel_seconds / 1e12,
+            "peak_unpacked": unpacked, "frac_unpacked": achieved / unpacked,
+            "coupled_steps": fine_steps, "launches": launches,
+            "avg_launch_ms": 1e3 * kernel_seconds / launches,
+            "valu_issue_util": valu_issue(precision, integrator)}
+
+
 def _cpu_model() -> str:
+    """The host CPU as /proc/cpuinfo names it: model name, family/model/stepping and
+    the clock of the first processor entry."""
+    fields = {}
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if not line.strip():
+                    break
+                k, _, v = line.partition(":")
+                fields[k.strip()] = v.strip()
     except OSError:
-        pass
-    return "unknown"
+        return "unknown"
+    return (f"{fields.get('model name', 'unknown')} (family {fields.get('cpu family', '?')}, "
+            f"model {fields.get('model', '?')}, stepping {fields.get('stepping', '?')}, "
+            f"{fields.get('cpu MHz', '?')} MHz)")
 
 
-def cpu_baseline(cfg, N_levels, target_steps=2.5e8, one_core_steps=1.2e7):
-    """The oracle on a bounded sample: each level's samples scaled down by the same
-    factor so the sample has about target_steps coupled fine steps, on all of the
-    oracle's threads; then a smaller sample of the same shape on one thread (the figure
-    to set beside the paper's single-core timings)."""
+def cpu_baseline(cfg, eps, fixed_L, N_init, one_core_steps=1.2e7):
+    """The oracle as it stands on this host: its own MLMC driver (plain schedule) on the
+    same estimate, giving time-to-eps and coupled particle-steps/s on all of the oracle's
+    threads; then a bounded sample of the same levels on one thread (the figure to set
+    beside the paper's single-core timings)."""
     import oracle
 
-    def run(steps_wanted):
-        total = sum(n * (cfg["M0"] << l) for l, n in enumerate(N_levels))
-        f = min(1.0, steps_wanted / total)
-        counts = [max(64, int(n * f)) for n in N_levels]
-        steps = sum(n * (cfg["M0"] << l) for l, n in enumerate(counts))
-        t0 = time.perf_counter()
-        for l, n in enumerate(counts):
-            oracle.level_sums(cfg, l, 0, n)
-        return f, counts, steps, time.perf_counter() - t0
-
     threads = oracle.num_threads()
-    f, counts, steps, dt = run(target_steps)
+    t0 = time.perf_counter()
+    r = oracle.estimate(eps, cfg, fixed_L=fixed_L, N_init=N_init, eps_is_relative=True)
+    dt = time.perf_counter() - t0
+    N = r["N"]
+    total = sum(n * (cfg["M0"] << l) for l, n in enumerate(N))
+    f1 = min(1.0, one_core_steps / total)
+    counts = [max(64, int(n * f1)) for n in N]
+    steps1 = sum(n * (cfg["M0"] << l) for l, n in enumerate(counts))
     oracle.set_num_threads(1)
     try:
-        f1, _, steps1, dt1 = run(one_core_steps)
+        t1 = time.perf_counter()
+        for l, n in enumerate(counts):
+            oracle.level_sums(cfg, l, 0, n)
+        dt1 = time.perf_counter() - t1
     finally:
         oracle.set_num_threads(threads)
-    return {"value": steps / dt, "unit": "coupled particle-steps/s", "cores": threads,
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = None
+    return {"value": r["fine_steps"] / dt, "unit": "coupled particle-steps/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"levels 0..{len(counts) - 1} of the same workload with N_l scaled by "
-                      f"{f:.3g} (N_l = {counts}), {steps:.3g} coupled fine steps, FP64, {dt:.1f} s",
-            "one_core": {"value": steps1 / dt1, "sample": f"N_l scaled by {f1:.3g}, {steps1:.3g} "
-                                                          f"coupled fine steps, {dt1:.1f} s"},
-            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count()}
+            "sample": f"the whole estimate by the oracle's own driver (plain schedule, FP64): "
+                      f"N_l = {N}, {r['fine_steps']:.3g} coupled fine steps, {dt:.1f} s",
+            "time_to_eps_s": dt, "estimate_m": r["estimate"], "rmse_est_m": r["rmse_est"],
+            "one_core": {"value": steps1 / dt1, "sample": f"each level's N_l scaled by {f1:.3g}, "
+                                                          f"{steps1:.3g} coupled fine steps, {dt1:.1f} s"},
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(), "cpus_usable": affinity}
 
 
 def _pct(xs, q):
@@ -592,41 +635,42 @@ def main():
     eps = W.SINGLE_LARGE_EPS_REL
     ws = torch.empty(ld.estimate_workspace_bytes(), dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream()
-    kw = dict(precision=args.precision, fixed_L=L, eps_is_relative=True, N_init=10000,
-              early_topup=not args.plain_schedule, workspace=ws, stream=stream)
+    kw = dict(fixed_L=L, eps_is_relative=True, N_init=10000, early_topup=not args.plain_schedule,
+              workspace=ws, stream=stream)
 
-    for _ in range(args.warmup):
-        ld.estimate(eps, cfg, **kw)
-    torch.cuda.synchronize()
-    results = []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        results.append(ld.estimate(eps, cfg, **kw))
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    def timed(precision):
+        """W untimed then K timed estimates in one precision: (results, seconds)."""
+        for _ in range(args.warmup):
+            ld.estimate(eps, cfg, precision=precision, **kw)
+        torch.cuda.synchronize()
+        out = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out.append(ld.estimate(eps, cfg, precision=precision, **kw))
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t0
 
-    fine_steps = sum(r["fine_steps"] for r in results)
+    def summary(precision, results, elapsed):
+        fs = sum(r["fine_steps"] for r in results)
+        dev_s = sum(r["device_seconds"] for r in results)
+        launches = sum(r["launches"] for r in results)
+        return fs, dev_s, launches, roofline(precision, args.integrator, fs, dev_s, launches)
+
+    results, elapsed = timed(args.precision)
+    fine_steps, dev_s, launches, roof = summary(args.precision, results, elapsed)
     value = fine_steps / elapsed
     # every integrator step, fine and coarse: sum_l N_l (M_l + M_{l-1}), M_{-1} = 0
     integ_steps = sum(n * ((cfg["M0"] << l) + ((cfg["M0"] << l) >> 1 if l > 0 else 0))
                       for r in results for l, n in enumerate(r["N"]))
 
-    # The same estimate with all-FP64 paths (time-to-eps), and the FP32 run's error
-    # against FP64 paths on identical draws and sample counts.
+    # The same estimate with the other path precision, timed alike, and the error of the
+    # run's paths against the other precision's on identical draws and sample counts.
     last = results[-1]
     other = "fp64" if args.precision == "fp32" else "fp32"
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    r_other = ld.estimate(eps, cfg, **dict(kw, precision=other))
-    torch.cuda.synchronize()
-    t_other = time.perf_counter() - t1
+    res_o, el_o = timed(other)
+    fs_o, dev_o, la_o, roof_o = summary(other, res_o, el_o)
     same = ld.level_sums_batch(cfg, [(l, 0, n) for l, n in enumerate(last["N"])], other)
     est_other_same_n = sum(s["sum_y"] / s["n"] for s in same)
-    dev_s = sum(r["device_seconds"] for r in results)
-    launches = sum(r["launches"] for r in results)
-    ops = OPS_PER_COUPLED_STEP[(args.integrator, cfg["profile"])]
-    achieved = ops * fine_steps / dev_s / 1e12
-    peak = PEAK_TFLOPS[args.precision]
     line = {
         "metric": "coupled particle-steps/s",
         "value": value,
@@ -650,15 +694,12 @@ def main():
                    "integrator_steps_per_s": integ_steps / elapsed,
                    "time_to_eps_s": last["wall_seconds"], "kernel_s_per_step": dev_s / args.steps,
                    "launches_per_step": launches / args.steps,
-                   f"time_to_eps_{other}_s": t_other,
-                   f"estimate_{other}_m": r_other["estimate"],
                    f"{args.precision}_minus_{other}_same_draws_m": last["estimate"] - est_other_same_n},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": hbm_traffic(args.precision),
-                     "kernel": f"level_kernel<{'float' if args.precision == 'fp32' else 'double'}>",
-                     "ops_per_coupled_step": ops,
-                     "avg_launch_ms": 1e3 * dev_s / launches,
-                     "valu_issue_util": valu_issue(args.precision)},
+        "roofline": roof,
+        other: {"value": fs_o / el_o, "unit": "coupled particle-steps/s", "steps": args.steps,
+                "warmup": args.warmup, "ms_per_step": 1e3 * el_o / args.steps,
+                "time_to_eps_s": res_o[-1]["wall_seconds"], "estimate_m": res_o[-1]["estimate"],
+                "N_l": res_o[-1]["N"], "kernel_s_per_step": dev_o / args.steps, "roofline": roof_o},
     }
     if args.serve_seconds > 0:
         rep = serving_report(ld, 100.0, args.serve_seconds, seed=11, n_init=args.n_init)
@@ -668,7 +709,7 @@ def main():
             line["serving"][key] = {k: r[k] for k in ("p50_ms", "p99_ms", "queries_per_s",
                                                       "coupled_steps_per_s", "max_running")}
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(dict(cfg), last["N"])
+        line["cpu_baseline"] = cpu_baseline(dict(cfg), eps, L, 10000)
     print(json.dumps(line), flush=True)
 
 
