@@ -94,6 +94,12 @@ struct Math<float> {
         const float z4 = z2 * z2;
         return __builtin_fmaf(z4, b, __builtin_fmaf(z2, a, z));
     }
+    // expm1(z) for |z| <= kTinyZ: the series to degree 3 (truncation below 2.6e-9
+    // relative, under half an FP32 ulp), z + z^2 (1/2 + z/6): two operations follow z.
+    static constexpr float kTinyZ = 0.00390625f;
+    static __device__ __forceinline__ float expm1_tiny(float z) {
+        return __builtin_fmaf(z * z, __builtin_fmaf(z, 1.0f / 6.0f, 0.5f), z);
+    }
 };
 
 template <>
@@ -162,6 +168,8 @@ struct Math<double> {
     // 1e-17 relative) in Estrin form:
     // z + z^2 (1/2 + z/6) + z^4 ((1/24 + z/120) + z^2 (1/720 + z/5040)).
     static constexpr double kSmallZ = 0.015625;
+    static constexpr double kTinyZ = 0.0;   // no shorter FP64 series: every tier-2 step takes the tier-1 one
+    static __device__ __forceinline__ double expm1_tiny(double z) { return expm1_small(z); }
     static __device__ __forceinline__ double expm1_small(double z) {
         const double z2 = z * z;
         const double a = fma(z, 1.0 / 6.0, 0.5);
@@ -346,27 +354,31 @@ __device__ __forceinline__ void fold_or_track(Path<R>& p, R H, uint32_t& key) {
     }
 }
 
-// expm1(-lambda h) of an O-step. SMALL: lambda_max h <= kSmallZ for this step size, so
-// the short series is exact to rounding for every X. The choice is made once per path
+// expm1(-lambda h) of an O-step by tier: 0 the full routine, 1 the short series
+// (lambda_max h <= kSmallZ for this step size), 2 the shortest (lambda_max h <= kTinyZ);
+// each is exact to rounding for every X of its steps. The tier is chosen once per path
 // from that path's own step size (h for a fine path, 2h for a coarse one), never inside
 // a step and never from how the samples are laid out on the device: a sample's bits do
 // not depend on the block mode that runs it.
-template <typename R, bool SMALL>
+template <typename R, int TIER>
 __device__ __forceinline__ R o_step_expm1(R z) {
-    if (SMALL) return Math<R>::expm1_small(z);
+    if (TIER == 2) return Math<R>::expm1_tiny(z);
+    if (TIER == 1) return Math<R>::expm1_small(z);
     return Math<R>::expm1_(z);
 }
 
-// True if the O-steps of size h may use the short expm1 series.
+// The expm1 tier of the O-steps of size h (symplectic Euler has none: tier 0).
 template <typename R>
-__device__ __forceinline__ bool small_steps(const KProblem& kp, double h) {
-    return kp.lam_max * h <= (double)Math<R>::kSmallZ;
+__device__ __forceinline__ int expm1_tier(const KProblem& kp, int integ, double h) {
+    if (integ == KINTEG_SE) return 0;
+    const double z = kp.lam_max * h;
+    return z <= (double)Math<R>::kTinyZ ? 2 : (z <= (double)Math<R>::kSmallZ ? 1 : 0);
 }
 
 // One step of size h. COARSE: xi is the combined extended noise and the physical noise
 // is S xi; otherwise xi is the physical noise and `tilde` receives S xi. `w` receives
-// e^{-lambda h} of the O-step (GL, BAOAB). SMALL: see o_step_expm1.
-template <typename R, int INTEG, int PROF, bool COARSE, bool SMALL, int FOLD>
+// e^{-lambda h} of the O-step (GL, BAOAB). TIER: see o_step_expm1.
+template <typename R, int INTEG, int PROF, bool COARSE, int TIER, int FOLD>
 __device__ __forceinline__ void step_impl(const Consts<R>& c, Path<R>& p, R h, R hh, R xi,
                                           R& tilde, R& w, uint32_t& key) {
     if (INTEG == KINTEG_SE) {                                        // Eq. (8)
@@ -385,7 +397,7 @@ __device__ __forceinline__ void step_impl(const Consts<R>& c, Path<R>& p, R h, R
         coeffs_at<R, PROF>(c, p.x, h, su, z, a, b);
         const R noise = COARSE ? Math<R>::flip(xi, p.sgn) : xi;
         if (!COARSE) tilde = Math<R>::flip(xi, p.sgn);
-        const R e1 = o_step_expm1<R, SMALL>(z);
+        const R e1 = o_step_expm1<R, TIER>(z);
         w = (R)1 + e1;
         const R sn = su * noise;
         const R us = Math<R>::fma_(sn, Math<R>::sqrt_(-e1 * ((R)2 + e1)), w * p.u);   // O
@@ -400,7 +412,7 @@ __device__ __forceinline__ void step_impl(const Consts<R>& c, Path<R>& p, R h, R
         o_coeffs<R, PROF>(c, p.x, h, su, z);
         const R noise = COARSE ? Math<R>::flip(xi, p.sgn) : xi;
         if (!COARSE) tilde = Math<R>::flip(xi, p.sgn);
-        const R e1 = o_step_expm1<R, SMALL>(z);
+        const R e1 = o_step_expm1<R, TIER>(z);
         w = (R)1 + e1;
         const R sn = su * noise;
         p.u = Math<R>::fma_(sn, Math<R>::sqrt_(-e1 * ((R)2 + e1)), w * p.u);   // O at X_{n+1/2}
@@ -412,11 +424,11 @@ __device__ __forceinline__ void step_impl(const Consts<R>& c, Path<R>& p, R h, R
 }
 
 // One step with every position update folded (Eq. 6, Sec. 4).
-template <typename R, int INTEG, int PROF, bool COARSE, bool SMALL>
+template <typename R, int INTEG, int PROF, bool COARSE, int TIER>
 __device__ __forceinline__ void step(const Consts<R>& c, Path<R>& p, R h, R hh, R xi,
                                      R& tilde, R& w) {
     uint32_t unused = 0;
-    step_impl<R, INTEG, PROF, COARSE, SMALL, FOLD_EXACT>(c, p, h, hh, xi, tilde, w, unused);
+    step_impl<R, INTEG, PROF, COARSE, TIER, FOLD_EXACT>(c, p, h, hh, xi, tilde, w, unused);
 }
 
 // Initial state shared by both paths of a sample.
@@ -456,35 +468,35 @@ __device__ __forceinline__ void init_path(const Consts<R>& c, Path<R>& p, R x0, 
 }
 
 // The time loop of one sample: M_l fine steps and, on levels >= 1, M_l / 2 coarse
-// steps driven by the combined fine noise. SMALL_F and SMALL_C: o_step_expm1's choice for
+// steps driven by the combined fine noise. TIER_F and TIER_C: o_step_expm1's tier for
 // the fine path (step h) and the coarse path (step 2h).
-template <typename R, int INTEG, int PROF, bool SMALL_F, bool SMALL_C>
+template <typename R, int INTEG, int PROF, int TIER_F, int TIER_C>
 __device__ __forceinline__ void run_paths(const Consts<R>& c, const Stream& st, int level,
                                           uint32_t M, R h, R hh, R h2, Path<R>& f, Path<R>& g) {
     R tilde_a, tilde_b, w_a, w_b, z0, z1;
     if (level == 0) {
         for (uint32_t m = 0; m < M / 2; ++m) {
             Normals<R>::pair(philox(st, m), z0, z1);
-            step<R, INTEG, PROF, false, SMALL_F>(c, f, h, hh, z0, tilde_a, w_a);
-            step<R, INTEG, PROF, false, SMALL_F>(c, f, h, hh, z1, tilde_b, w_b);
+            step<R, INTEG, PROF, false, TIER_F>(c, f, h, hh, z0, tilde_a, w_a);
+            step<R, INTEG, PROF, false, TIER_F>(c, f, h, hh, z1, tilde_b, w_b);
         }
         if (M & 1u) {
             Normals<R>::pair(philox(st, M / 2), z0, z1);
-            step<R, INTEG, PROF, false, SMALL_F>(c, f, h, hh, z0, tilde_a, w_a);
+            step<R, INTEG, PROF, false, TIER_F>(c, f, h, hh, z0, tilde_a, w_a);
         }
         return;
     }
     for (uint32_t m = 0; m < M / 2; ++m) {
         Normals<R>::pair(philox(st, m), z0, z1);
-        step<R, INTEG, PROF, false, SMALL_F>(c, f, h, hh, z0, tilde_a, w_a);   // fine step 2m
-        step<R, INTEG, PROF, false, SMALL_F>(c, f, h, hh, z1, tilde_b, w_b);   // fine step 2m+1
+        step<R, INTEG, PROF, false, TIER_F>(c, f, h, hh, z0, tilde_a, w_a);   // fine step 2m
+        step<R, INTEG, PROF, false, TIER_F>(c, f, h, hh, z1, tilde_b, w_b);   // fine step 2m+1
         R xi_c;
         if (INTEG == KINTEG_SE)
             xi_c = (tilde_a + tilde_b) * (R)0.70710678118654752440;  // Eq. (18)
         else
             xi_c = (w_a * tilde_a + tilde_b) * Math<R>::rsqrt(w_a * w_a + (R)1);   // Eq. (19)
         R unused_t, unused_w;
-        step<R, INTEG, PROF, true, SMALL_C>(c, g, h2, h, xi_c, unused_t, unused_w);
+        step<R, INTEG, PROF, true, TIER_C>(c, g, h2, h, xi_c, unused_t, unused_w);
     }
 }
 
@@ -571,16 +583,20 @@ __device__ __forceinline__ void run_sample(const KProblem& kp, const Consts<R>& 
     const R h = (R)hd, hh = (R)(0.5 * hd), h2 = (R)(2.0 * hd);
     init_path<R, INTEG, PROF>(c, f, x0, u0, hh);
     init_path<R, INTEG, PROF>(c, g, x0, u0, h);
-    // each path by its own step: h for the fine path, 2h for the coarse one (a short
-    // series that holds for 2h holds for h too); symplectic Euler has no expm1
-    const bool sf = INTEG != KINTEG_SE && small_steps<R>(kp, hd);
-    const bool sc = INTEG != KINTEG_SE && level != 0 && small_steps<R>(kp, 2.0 * hd);
-    if (sc)
-        run_paths<R, INTEG, PROF, true, true>(c, st, level, M, h, hh, h2, f, g);
-    else if (sf)
-        run_paths<R, INTEG, PROF, true, false>(c, st, level, M, h, hh, h2, f, g);
+    // each path by its own step: h for the fine path, 2h for the coarse one (the tier of
+    // the coarse step never exceeds the fine step's); level 0 has no coarse path
+    const int tf = expm1_tier<R>(kp, INTEG, hd);
+    const int tc = level == 0 ? tf : expm1_tier<R>(kp, INTEG, 2.0 * hd);
+    if (tc == 2)
+        run_paths<R, INTEG, PROF, 2, 2>(c, st, level, M, h, hh, h2, f, g);
+    else if (tf == 2)
+        run_paths<R, INTEG, PROF, 2, 1>(c, st, level, M, h, hh, h2, f, g);
+    else if (tc == 1)
+        run_paths<R, INTEG, PROF, 1, 1>(c, st, level, M, h, hh, h2, f, g);
+    else if (tf == 1)
+        run_paths<R, INTEG, PROF, 1, 0>(c, st, level, M, h, hh, h2, f, g);
     else
-        run_paths<R, INTEG, PROF, false, false>(c, st, level, M, h, hh, h2, f, g);
+        run_paths<R, INTEG, PROF, 0, 0>(c, st, level, M, h, hh, h2, f, g);
 }
 
 // Quantity of interest in FP64 (Sec. 2, Sec. 5).

@@ -192,7 +192,7 @@ struct PipeLds {
 // chain of its steps. A lane whose positions left [0, H] repeats the chunk from its
 // saved state with folded steps and publishes again, so every lane ends with the
 // folded steps' results bit for bit.
-template <typename R, int INTEG, int PROF, bool SMALL>
+template <typename R, int INTEG, int PROF, int TIER>
 __device__ __forceinline__ void pipe_fine_chunk(const Consts<R>& c, Path<R>& p, R h, R hh,
                                                 PipeLds<R>& L, uint32_t b, uint32_t m0,
                                                 uint32_t P, int lane) {
@@ -201,8 +201,8 @@ __device__ __forceinline__ void pipe_fine_chunk(const Consts<R>& c, Path<R>& p, 
     for (int j = 0; j < kPipeChunk; ++j) {
         if (m0 + j < P) {
             R ta, tb, wa, wb;
-            step_impl<R, INTEG, PROF, false, SMALL, FOLD_TRACK>(c, p, h, hh, L.nrm[b][j][0][lane], ta, wa, key);
-            step_impl<R, INTEG, PROF, false, SMALL, FOLD_TRACK>(c, p, h, hh, L.nrm[b][j][1][lane], tb, wb, key);
+            step_impl<R, INTEG, PROF, false, TIER, FOLD_TRACK>(c, p, h, hh, L.nrm[b][j][0][lane], ta, wa, key);
+            step_impl<R, INTEG, PROF, false, TIER, FOLD_TRACK>(c, p, h, hh, L.nrm[b][j][1][lane], tb, wb, key);
             L.msg[b][j][0][lane] = ta;
             L.msg[b][j][1][lane] = tb;
             L.msg[b][j][2][lane] = wa;
@@ -214,8 +214,8 @@ __device__ __forceinline__ void pipe_fine_chunk(const Consts<R>& c, Path<R>& p, 
         for (int j = 0; j < kPipeChunk; ++j) {
             if (m0 + j < P) {
                 R ta, tb, wa, wb;
-                step<R, INTEG, PROF, false, SMALL>(c, p, h, hh, L.nrm[b][j][0][lane], ta, wa);
-                step<R, INTEG, PROF, false, SMALL>(c, p, h, hh, L.nrm[b][j][1][lane], tb, wb);
+                step<R, INTEG, PROF, false, TIER>(c, p, h, hh, L.nrm[b][j][0][lane], ta, wa);
+                step<R, INTEG, PROF, false, TIER>(c, p, h, hh, L.nrm[b][j][1][lane], tb, wb);
                 L.msg[b][j][0][lane] = ta;
                 L.msg[b][j][1][lane] = tb;
                 L.msg[b][j][2][lane] = wa;
@@ -225,11 +225,12 @@ __device__ __forceinline__ void pipe_fine_chunk(const Consts<R>& c, Path<R>& p, 
 }
 
 // Coarse wave: the K coarse steps of one chunk, each driven by the combined noise of
-// its fine pair (Eq. 18 for SE, Eq. 19 otherwise).
-template <typename R, int INTEG, int PROF, bool SMALL>
-__device__ __forceinline__ void pipe_coarse_chunk(const Consts<R>& c, Path<R>& p, R h2, R h,
-                                                  PipeLds<R>& L, uint32_t b, uint32_t m0,
-                                                  uint32_t P, int lane) {
+// its fine pair (Eq. 18 for SE, Eq. 19 otherwise). Like the fine wave, the chunk runs
+// without folds first and a lane whose positions left [0, H] repeats it with them.
+template <typename R, int INTEG, int PROF, int FOLD, int TIER>
+__device__ __forceinline__ void coarse_steps(const Consts<R>& c, Path<R>& p, R h2, R h,
+                                             PipeLds<R>& L, uint32_t b, uint32_t m0,
+                                             uint32_t P, int lane, uint32_t& key) {
     for (int j = 0; j < kPipeChunk; ++j) {
         if (m0 + j < P) {
             const R ta = L.msg[b][j][0][lane], tb = L.msg[b][j][1][lane];
@@ -241,8 +242,21 @@ __device__ __forceinline__ void pipe_coarse_chunk(const Consts<R>& c, Path<R>& p
                 xi_c = (wa * ta + tb) * Math<R>::rsqrt(wa * wa + (R)1);  // Eq. (19)
             }
             R unused_t, unused_w;
-            step<R, INTEG, PROF, true, SMALL>(c, p, h2, h, xi_c, unused_t, unused_w);
+            step_impl<R, INTEG, PROF, true, TIER, FOLD>(c, p, h2, h, xi_c, unused_t, unused_w, key);
         }
+    }
+}
+
+template <typename R, int INTEG, int PROF, int TIER>
+__device__ __forceinline__ void pipe_coarse_chunk(const Consts<R>& c, Path<R>& p, R h2, R h,
+                                                  PipeLds<R>& L, uint32_t b, uint32_t m0,
+                                                  uint32_t P, int lane) {
+    const Path<R> p0 = p;
+    uint32_t key = 0;
+    coarse_steps<R, INTEG, PROF, FOLD_TRACK, TIER>(c, p, h2, h, L, b, m0, P, lane, key);
+    if (__builtin_expect(key > FoldKey<R>::limit(c.H), 0)) {
+        p = p0;
+        coarse_steps<R, INTEG, PROF, FOLD_EXACT, TIER>(c, p, h2, h, L, b, m0, P, lane, key);
     }
 }
 
@@ -263,9 +277,9 @@ __device__ __forceinline__ void pipe_samples(const KProblem& kp, const Consts<R>
     const uint32_t nch = (P + K - 1) / K;
     const double hd = kp.T / (double)M;
     const R h = (R)hd, hh = (R)(0.5 * hd), h2 = (R)(2.0 * hd);
-    // o_step_expm1's choice per path from its own step, as in run_sample (SE has no expm1)
-    const bool small_f = INTEG != KINTEG_SE && small_steps<R>(kp, hd);
-    const bool small_c = INTEG != KINTEG_SE && small_steps<R>(kp, 2.0 * hd);
+    // o_step_expm1's tier per path from its own step, as in run_sample
+    const int tier_f = expm1_tier<R>(kp, INTEG, hd);
+    const int tier_c = expm1_tier<R>(kp, INTEG, 2.0 * hd);
     const Stream st = make_stream(kp.seed, kp.stream_id, level, item.sample_begin + local);
     Path<R> p;
     if (wave >= 2) {
@@ -291,18 +305,22 @@ __device__ __forceinline__ void pipe_samples(const KProblem& kp, const Consts<R>
         } else if (wave == 2) {
             if (s >= 1 && s <= nch) {
                 const uint32_t b = (s - 1) & 1;
-                if (small_f)
-                    pipe_fine_chunk<R, INTEG, PROF, true>(c, p, h, hh, L, b, (s - 1) * K, P, lane);
+                if (tier_f == 2)
+                    pipe_fine_chunk<R, INTEG, PROF, 2>(c, p, h, hh, L, b, (s - 1) * K, P, lane);
+                else if (tier_f == 1)
+                    pipe_fine_chunk<R, INTEG, PROF, 1>(c, p, h, hh, L, b, (s - 1) * K, P, lane);
                 else
-                    pipe_fine_chunk<R, INTEG, PROF, false>(c, p, h, hh, L, b, (s - 1) * K, P, lane);
+                    pipe_fine_chunk<R, INTEG, PROF, 0>(c, p, h, hh, L, b, (s - 1) * K, P, lane);
             }
         } else {
             if (s >= 2) {
                 const uint32_t b = s & 1;   // == (s - 2) & 1
-                if (small_c)
-                    pipe_coarse_chunk<R, INTEG, PROF, true>(c, p, h2, h, L, b, (s - 2) * K, P, lane);
+                if (tier_c == 2)
+                    pipe_coarse_chunk<R, INTEG, PROF, 2>(c, p, h2, h, L, b, (s - 2) * K, P, lane);
+                else if (tier_c == 1)
+                    pipe_coarse_chunk<R, INTEG, PROF, 1>(c, p, h2, h, L, b, (s - 2) * K, P, lane);
                 else
-                    pipe_coarse_chunk<R, INTEG, PROF, false>(c, p, h2, h, L, b, (s - 2) * K, P, lane);
+                    pipe_coarse_chunk<R, INTEG, PROF, 0>(c, p, h2, h, L, b, (s - 2) * K, P, lane);
             }
         }
         __syncthreads();

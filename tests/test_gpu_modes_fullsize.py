@@ -53,20 +53,24 @@ def _lam_max(cfg):
     return su / (cfg["kappa_tau"] * e)
 
 
-# Levels where the short expm1 series holds for the fine step h but not for the coarse
-# step 2h (lambda_max h <= z_small < 2 lambda_max h; z_small = 1/16 in FP32, 1/64 in FP64):
-# there the two paths of a sample take different expm1 code, in either block mode.
-BOUNDARY = [("BAOAB", "fp32", 40, 5), ("GL", "fp32", 40, 5), ("BAOAB", "fp32", 8, 7), ("GL", "fp32", 8, 7),
-            ("BAOAB", "fp64", 40, 7), ("GL", "fp64", 40, 7), ("BAOAB", "fp64", 8, 9), ("GL", "fp64", 8, 9)]
+# Levels where a shorter expm1 series holds for the fine step h but not for the coarse
+# step 2h (lambda_max h <= z < 2 lambda_max h): z = 1/16 (FP32) or 1/64 (FP64) between
+# the full routine and the short series, z = 2^-8 (FP32) between the short series and
+# the shortest. There the two paths of a sample take different expm1 code, in either
+# block mode.
+BOUNDARY = [("BAOAB", "fp32", 40, 5, 1 / 16), ("GL", "fp32", 40, 5, 1 / 16),
+            ("BAOAB", "fp32", 8, 7, 1 / 16), ("GL", "fp32", 8, 7, 1 / 16),
+            ("BAOAB", "fp64", 40, 7, 1 / 64), ("GL", "fp64", 40, 7, 1 / 64),
+            ("BAOAB", "fp64", 8, 9, 1 / 64), ("GL", "fp64", 8, 9, 1 / 64),
+            ("BAOAB", "fp32", 8, 11, 2.0 ** -8), ("GL", "fp32", 40, 9, 2.0 ** -8)]
 
 
-@pytest.mark.parametrize("integ,prec,M0,level", BOUNDARY)
-def test_pipe_and_stream_agree_on_the_short_series_boundary_level(integ, prec, M0, level):
+@pytest.mark.parametrize("integ,prec,M0,level,z", BOUNDARY)
+def test_pipe_and_stream_agree_on_the_short_series_boundary_level(integ, prec, M0, level, z):
     cfg = W.neutral(500.0, integ, M0=M0)
     h = cfg["T"] / (M0 << level)
-    z_small = 1.0 / 16 if prec == "fp32" else 1.0 / 64
     lam = _lam_max(cfg)
-    assert lam * h <= z_small < 2.0 * lam * h
+    assert lam * h <= z < 2.0 * lam * h
     say(f"case boundary {integ} {prec} M0={M0} level={level}")
     pipe = ld.level_samples(cfg, level, 3, PIPE_MAX, prec)        # PIPE blocks
     stream = ld.level_samples(cfg, level, 3, PIPE_MAX + 1, prec)  # STREAM blocks
