@@ -1,12 +1,15 @@
 // engine.cpp -- many MLMC estimates in one persistent launch per iteration.
 //
 // Each active query owns a slot: its problem parameters and its running level sums
-// (LD_MAX_LEVELS ld_level_sums) live in device memory for the query's lifetime. An
-// iteration gathers every query's planned (level, range) pairs, cuts them into tiles
-// with a rule that depends on the range alone, uploads the tile and range tables, and
-// replays a captured graph: reset queue counters -> persistent kernel per queue (profile
-// kind, or adaptive symplectic Euler) ->
-// merge of each range's partials into the running sums. The running sums of the
+// (LD_MAX_LEVELS ld_level_sums) live in device memory for the query's lifetime.
+// Submission touches no device: the problem waits in a pinned host table and goes up
+// with the next iteration's tables, and a slot's level sums restart from zero at the
+// merge of its first range. An iteration gathers every query's planned (level, range)
+// pairs, cuts them into tiles with a rule that depends on the range alone, writes the
+// tile and range tables into pinned staging, uploads them (and the new problems) with
+// one copy each, and replays a captured graph: reset queue counters -> persistent
+// kernel per queue (profile kind, or adaptive symplectic Euler) -> merge of each
+// range's partials into the running sums. The running sums of the
 // touched slots come back and each query's planner (mlmc_plan, Sec. 3.3 / Sec. 6)
 // decides its next samples; converged queries leave, new ones are admitted between
 // iterations (continuous batching).
@@ -43,6 +46,7 @@ struct Query {
     int32_t iterations = 0;
     int status = LD_PENDING;
     double t_submit = 0, t_done = 0;
+    uint32_t fresh_levels = 0;   // levels whose running sums no range has reached yet
     ld_level_sums sums[LD_MAX_LEVELS];
 };
 
@@ -71,7 +75,10 @@ struct ld_engine {
     ld_level_sums* d_partials = nullptr;
     KHeader* h_hdr = nullptr;
     KRange* h_ranges = nullptr;
-    KTile* h_tiles = nullptr;
+    KTile* h_tiles = nullptr;              // pinned tile staging, h_tile_cap tiles (grows)
+    uint64_t h_tile_cap = 0;
+    KProblem* h_problems = nullptr;        // pinned copy of every slot's problem
+    int32_t new_lo = 0, new_hi = -1;       // slots whose problems await upload
     ld_level_sums* h_running = nullptr;
     hipGraphExec_t graph[1 << kNumQueues] = {};   // by queue mask
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -116,6 +123,7 @@ void release_resources(ld_engine* e) {
     if (e->h_hdr) (void)hipHostFree(e->h_hdr);
     if (e->h_ranges) (void)hipHostFree(e->h_ranges);
     if (e->h_tiles) (void)hipHostFree(e->h_tiles);
+    if (e->h_problems) (void)hipHostFree(e->h_problems);
     if (e->h_running) (void)hipHostFree(e->h_running);
     if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
 }
@@ -135,9 +143,10 @@ void stream_tiles(const ld_engine* e, const Query& qu, uint64_t n, uint32_t* spl
     *nb = (uint32_t)((n + per * s - 1) / (per * s));
 }
 
-// Tiles of one range; the rule depends on the range alone.
-void tile_range(const ld_engine* e, uint32_t slot, const Query& qu, int32_t level, uint64_t begin,
-                uint64_t n, uint16_t prio, std::vector<KTile>& out) {
+// Tiles of one range, written to out[0..]; the rule depends on the range alone. Returns
+// the number of tiles (tiles_of_range).
+uint64_t tile_range(const ld_engine* e, uint32_t slot, const Query& qu, int32_t level, uint64_t begin,
+                    uint64_t n, uint16_t prio, KTile* out) {
     const uint64_t M = (uint64_t)qu.prob.M0 << level;
     KTile t;
     std::memset(&t, 0, sizeof t);
@@ -152,9 +161,9 @@ void tile_range(const ld_engine* e, uint32_t slot, const Query& qu, int32_t leve
         const uint64_t nb = (n + 63) / 64;
         for (uint64_t b = 0; b < nb; ++b) {
             t.local_block = (uint32_t)b;
-            out.push_back(t);
+            out[b] = t;
         }
-        return;
+        return nb;
     }
     uint32_t spl = 1, nb = 0;
     stream_tiles(e, qu, n, &spl, &nb);
@@ -162,8 +171,24 @@ void tile_range(const ld_engine* e, uint32_t slot, const Query& qu, int32_t leve
     t.spl = spl;
     for (uint64_t b = 0; b < nb; ++b) {
         t.local_block = (uint32_t)b;
-        out.push_back(t);
+        out[b] = t;
     }
+    return nb;
+}
+
+// Pinned tile staging for at least n tiles. Called only between iterations: the previous
+// iteration's upload from the old buffer has completed (its step synchronised).
+int reserve_tiles(ld_engine* e, uint64_t n) {
+    if (n <= e->h_tile_cap) return LD_OK;
+    uint64_t cap = std::max<uint64_t>(e->h_tile_cap, 4096);
+    while (cap < n) cap *= 2;
+    cap = std::min<uint64_t>(cap, std::max<uint64_t>(e->max_tiles, n));
+    KTile* p = nullptr;
+    if (hipHostMalloc((void**)&p, cap * sizeof(KTile)) != hipSuccess) return fail(LD_ENOMEM, "pinned tile staging failed");
+    if (e->h_tiles) (void)hipHostFree(e->h_tiles);
+    e->h_tiles = p;
+    e->h_tile_cap = cap;
+    return LD_OK;
 }
 
 uint64_t tiles_of_range(const ld_engine* e, const Query& qu, int32_t level, uint64_t n) {
@@ -285,12 +310,14 @@ int ld_engine_create(const ld_engine_opts* opts_in, ld_engine** out) {
     e->d_partials = (ld_level_sums*)(b + o_part);
     if (hipHostMalloc((void**)&e->h_hdr, sizeof(KHeader)) != hipSuccess ||
         hipHostMalloc((void**)&e->h_ranges, e->max_ranges * sizeof(KRange)) != hipSuccess ||
-        hipHostMalloc((void**)&e->h_running, slots * LD_MAX_LEVELS * sizeof(ld_level_sums)) != hipSuccess) {
+        hipHostMalloc((void**)&e->h_running, slots * LD_MAX_LEVELS * sizeof(ld_level_sums)) != hipSuccess ||
+        hipHostMalloc((void**)&e->h_problems, slots * sizeof(KProblem)) != hipSuccess ||
+        reserve_tiles(e, std::min<uint64_t>(e->max_tiles, 65536)) != LD_OK) {
         release_resources(e);
         delete e;
         return fail(LD_ENOMEM, "pinned host staging allocation failed");
     }
-    // tile staging grows on demand (pinned), starting small
+    std::memset(e->h_problems, 0, slots * sizeof(KProblem));
     if (o.hip_stream != nullptr) {
         e->stream = (hipStream_t)o.hip_stream;
     } else {
@@ -352,13 +379,13 @@ int ld_engine_submit(ld_engine* e, const ld_query* qq, int64_t* handle) {
     std::memset(qu.sums, 0, sizeof qu.sums);
     std::memset(&qu.plan, 0, sizeof qu.plan);
     for (int32_t l = 0; l <= qu.L; ++l) qu.dn[l] = qq->N_init;
+    qu.fresh_levels = ~0u;
     qu.t_submit = now_seconds();
-    if (hipMemcpyAsync(&e->d_problems[slot], &qu.kp, sizeof(KProblem), hipMemcpyHostToDevice, e->stream) !=
-            hipSuccess ||
-        launch_clear_sums(&e->d_running[slot * LD_MAX_LEVELS], LD_MAX_LEVELS, e->stream) != LD_OK) {
-        qu.used = false;
-        return fail(LD_EDEVICE, "uploading the query failed");
-    }
+    // no device work here: the problem goes up with the next iteration's tables (the
+    // previous iteration's copies from this staging have completed)
+    e->h_problems[slot] = qu.kp;
+    e->new_lo = (e->new_hi < 0) ? slot : std::min(e->new_lo, slot);
+    e->new_hi = std::max(e->new_hi, slot);
     *handle = qu.handle;
     return LD_OK;
 }
@@ -385,60 +412,75 @@ int ld_engine_step(ld_engine* e, int32_t* n_active) {
     std::stable_sort(pend.begin(), pend.end(),
                      [&](const Pending& a, const Pending& b) { return steps_of(a) > steps_of(b); });
     const double top = steps_of(pend.front());
-    // 2. tiles, grouped by queue (profile kind, or adaptive SE); ranges that do not fit
-    //    wait for the next iteration
-    std::vector<KTile> tiles[kNumQueues];
-    std::vector<KRange> ranges[kNumQueues];
-    std::vector<Pending> taken[kNumQueues];
+    // 2. the ranges that fit, grouped by queue (profile kind, or adaptive SE); ranges
+    //    that do not fit wait for the next iteration
+    struct Taken {
+        Pending p;
+        int qi;
+        uint64_t nt;
+        uint16_t prio;
+    };
+    std::vector<Taken> taken;
+    uint64_t count[kNumQueues] = {0, 0, 0};
     uint64_t total = 0;
     for (const Pending& p : pend) {
         const Query& qu = e->q[p.slot];
         const uint64_t nt = tiles_of_range(e, qu, p.level, p.n);
-        size_t n_ranges = 0;
-        for (const auto& v : ranges) n_ranges += v.size();
-        if (total + nt > e->max_tiles || n_ranges >= e->max_ranges) continue;
+        if (total + nt > e->max_tiles || taken.size() >= e->max_ranges) continue;
         const int qi = qu.kp.adaptive ? (int)KQUEUE_ADAPT : qu.kp.profile;
         const uint16_t prio = (uint16_t)std::max(0, 3 - (int)std::lround(std::log2(top / steps_of(p))));
-        KRange r;
-        r.slot = (uint32_t)p.slot;
-        r.level = p.level;
-        r.tile_begin = (uint32_t)tiles[qi].size();
-        tile_range(e, (uint32_t)p.slot, qu, p.level, p.begin, p.n, prio, tiles[qi]);
-        r.n_tiles = (uint32_t)(tiles[qi].size() - r.tile_begin);
-        ranges[qi].push_back(r);
-        taken[qi].push_back(p);
+        taken.push_back({p, qi, nt, prio});
+        count[qi] += nt;
         total += nt;
     }
     if (total == 0) return fail(LD_ENOMEM, "a single range exceeds the engine's tile budget");
-    // concatenate the queues: neutral, homogeneous, adaptive
+    int rc = reserve_tiles(e, total);
+    if (rc != LD_OK) return rc;
+    // the queues one after the other in the tile table: neutral, homogeneous, adaptive;
+    // tiles and ranges are written straight into the pinned staging
     const int order[kNumQueues] = {KPROFILE_NEUTRAL, KPROFILE_HOMOGENEOUS, KQUEUE_ADAPT};
-    std::vector<KTile> all;
-    std::vector<KRange> rall;
-    std::vector<Pending> pall;
     std::memset(e->h_hdr, 0, sizeof(KHeader));
     uint32_t mask = 0;
+    uint64_t first = 0;
+    std::vector<Pending> pall;
+    uint32_t nr = 0;
     for (int qi : order) {
-        const uint32_t first = (uint32_t)all.size(), n = (uint32_t)tiles[qi].size();
-        all.insert(all.end(), tiles[qi].begin(), tiles[qi].end());
-        for (KRange r : ranges[qi]) {
-            r.tile_begin += first;
-            rall.push_back(r);
+        e->h_hdr->queue[qi] = KQueue{(uint32_t)first, (uint32_t)count[qi], (uint32_t)qi, 0};
+        if (count[qi] > 0) mask |= 1u << qi;
+        uint64_t cursor = first;
+        for (const Taken& t : taken) {
+            if (t.qi != qi) continue;
+            Query& qu = e->q[t.p.slot];
+            KRange& r = e->h_ranges[nr++];
+            std::memset(&r, 0, sizeof r);
+            r.slot = (uint32_t)t.p.slot;
+            r.level = t.p.level;
+            r.tile_begin = (uint32_t)cursor;
+            r.n_tiles = (uint32_t)tile_range(e, (uint32_t)t.p.slot, qu, t.p.level, t.p.begin, t.p.n, t.prio,
+                                             e->h_tiles + cursor);
+            r.fresh = (qu.fresh_levels >> t.p.level) & 1u;
+            cursor += r.n_tiles;
+            pall.push_back(t.p);
         }
-        pall.insert(pall.end(), taken[qi].begin(), taken[qi].end());
-        e->h_hdr->queue[qi] = KQueue{first, n, (uint32_t)qi, 0};
-        if (n > 0) mask |= 1u << qi;
+        first += count[qi];
     }
-    e->h_hdr->n_ranges = (uint32_t)rall.size();
-    std::memcpy(e->h_ranges, rall.data(), rall.size() * sizeof(KRange));
-    // 3. upload, run, read back
+    e->h_hdr->n_ranges = nr;
+    // 3. upload (new problems, header, ranges, tiles: one copy each), run, read back
+    if (e->new_hi >= 0 &&
+        hipMemcpyAsync(&e->d_problems[e->new_lo], &e->h_problems[e->new_lo],
+                       (size_t)(e->new_hi - e->new_lo + 1) * sizeof(KProblem), hipMemcpyHostToDevice,
+                       e->stream) != hipSuccess)
+        return fail(LD_EDEVICE, "uploading the new problems failed");
+    e->new_lo = 0;
+    e->new_hi = -1;
     if (hipMemcpyAsync(e->d_hdr, e->h_hdr, sizeof(KHeader), hipMemcpyHostToDevice, e->stream) != hipSuccess ||
-        hipMemcpyAsync(e->d_ranges, e->h_ranges, rall.size() * sizeof(KRange), hipMemcpyHostToDevice,
-                       e->stream) != hipSuccess ||
-        hipMemcpyAsync(e->d_tiles, all.data(), all.size() * sizeof(KTile), hipMemcpyHostToDevice, e->stream) !=
+        hipMemcpyAsync(e->d_ranges, e->h_ranges, nr * sizeof(KRange), hipMemcpyHostToDevice, e->stream) !=
+            hipSuccess ||
+        hipMemcpyAsync(e->d_tiles, e->h_tiles, total * sizeof(KTile), hipMemcpyHostToDevice, e->stream) !=
             hipSuccess)
         return fail(LD_EDEVICE, "uploading the tile tables failed");
     if (e->opts.use_graph && e->graph[mask] == nullptr) {
-        int rc = capture_graph(e, mask);
+        rc = capture_graph(e, mask);
         if (rc != LD_OK) return rc;
     }
     (void)hipEventRecord(e->ev0, e->stream);
@@ -446,7 +488,7 @@ int ld_engine_step(ld_engine* e, int32_t* n_active) {
         if (hipGraphLaunch(e->graph[mask], e->stream) != hipSuccess)
             return fail(LD_EDEVICE, "hipGraphLaunch failed");
     } else {
-        int rc = launch_engine_iteration(e->opts.precision, e->grid, mask, e->d_hdr, e->d_tiles, e->d_problems,
+        rc = launch_engine_iteration(e->opts.precision, e->grid, mask, e->d_hdr, e->d_tiles, e->d_problems,
                                          e->d_partials, e->d_counters, e->d_ranges, e->d_running,
                                          e->d_range_out, e->stream);
         if (rc != LD_OK) return fail(rc, "engine launch failed");
@@ -471,6 +513,7 @@ int ld_engine_step(ld_engine* e, int32_t* n_active) {
         Query& qu = e->q[p.slot];
         qu.drawn[p.level] += p.n;
         qu.dn[p.level] = 0;
+        qu.fresh_levels &= ~(1u << p.level);
         e->fine_steps += (double)p.n * (double)((uint64_t)qu.prob.M0 << p.level);
         ran.push_back(p.slot);
     }

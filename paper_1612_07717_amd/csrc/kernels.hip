@@ -652,15 +652,23 @@ __global__ __launch_bounds__(kBlock) void merge_ranges_kernel(const KHeader* __r
         if (wave_index() == 0) {   // scalar branch; every lane computes and stores the same values
             store_sums(&range_out[r], acc);
             ld_level_sums* run = &running[rg.slot * LD_MAX_LEVELS + rg.level];
+            // a fresh level adds to zeros: the same arithmetic as after clearing it
             Acc tot;
+            if (rg.fresh) {
+                acc_zero(tot);
+            } else {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                tot.s[k] = run->s[k];
-                tot.c[k] = run->c[k];
-                neumaier_merge(tot.s[k], tot.c[k], acc.s[k], acc.c[k]);
+                for (int k = 0; k < 4; ++k) {
+                    tot.s[k] = run->s[k];
+                    tot.c[k] = run->c[k];
+                }
+                tot.n = run->n;
+                tot.nbad = run->n_nonfinite;
             }
-            tot.n = run->n + acc.n;
-            tot.nbad = run->n_nonfinite + acc.nbad;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) neumaier_merge(tot.s[k], tot.c[k], acc.s[k], acc.c[k]);
+            tot.n += acc.n;
+            tot.nbad += acc.nbad;
             store_sums(run, tot);
         }
     }

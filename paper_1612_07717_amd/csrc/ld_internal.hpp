@@ -111,12 +111,16 @@ struct KHeader {
     uint32_t pad[3];
 };
 
-// A range's tiles are contiguous: partials [tile_begin, tile_begin + n_tiles).
+// A range's tiles are contiguous: partials [tile_begin, tile_begin + n_tiles). fresh:
+// the first range of this (slot, level) since the slot was taken, so its running sums
+// start from zero (whatever an earlier query left there).
 struct KRange {
     uint32_t slot;
     int32_t level;
     uint32_t tile_begin;
     uint32_t n_tiles;
+    uint32_t fresh;
+    uint32_t pad[3];
 };
 
 constexpr int kMergeGrid = 256;   // blocks of the range-merge kernel (grid-stride)
