@@ -451,16 +451,21 @@ def adaptive_report(ld, precisions=("fp64", "fp32"), n_bias=1 << 22):
     return out
 
 
-def batched_report(ld, steps, warmup):
+def batched_report(ld, steps, warmup, autotune=True):
     """64 independent estimators (mixed release height, tolerance, integrator and QoI)
-    in one live engine: autotuned FP32, the same options in FP64 (also the one-call form
-    that creates its engine), and the same queries one at a time through mlmc_estimate
-    in FP64 with a preallocated workspace."""
+    in one live engine: autotuned FP32 (or the default options), the same options in
+    FP64 (also the one-call form that creates its engine), and the same queries one at a
+    time through mlmc_estimate in FP64 with a preallocated workspace. Each precision's
+    roofline counts the algorithmic operations of every query's coupled steps over the
+    engine's kernel time (HIP events around each iteration's graph)."""
     import torch
     spec = W.batched_estimators(64)
     queries = [ld.make_query(q["problem"], q["eps"], eps_is_relative=q["eps_is_relative"],
                              N_init=BATCHED_N_INIT) for q in spec]
-    best, t_tune = ld.autotune(queries, reps=3, precision="fp32")   # median of 3 per configuration
+    if autotune:
+        best, t_tune = ld.autotune(queries, reps=3, precision="fp32")   # median of 3 per configuration
+    else:
+        best, t_tune = ld.engine_opts(precision="fp32"), 0.0
     def run_all(engine):
         """All queries to completion on a live engine (submitted as slots free up)."""
         handles, out, nxt = [None] * len(queries), [None] * len(queries), 0
@@ -488,16 +493,28 @@ def batched_report(ld, steps, warmup):
             for _ in range(warmup):
                 run_all(eng)
             torch.cuda.synchronize()
+            dev0 = eng.stats()["device_seconds"]
             t0 = time.perf_counter()
             for _ in range(steps):
                 out = run_all(eng)
             dt = (time.perf_counter() - t0) / steps
+            dev_s = (eng.stats()["device_seconds"] - dev0) / steps
         # the one-call form, which creates and frees an engine (about 1 GiB) each time
         t0 = time.perf_counter()
         ld.estimate_batch(queries, opts=o)
         dt_once = time.perf_counter() - t0
         fs = sum(r["fine_steps"] for r in out)
+        ops = sum(r["fine_steps"] * FP_OPS_PER_COUPLED_STEP[q["problem"]["integrator"]]
+                  for r, q in zip(out, spec))
+        achieved = ops / dev_s / 1e12
         res[prec] = {"seconds": dt, "coupled_steps_per_s": fs / dt, "fine_steps": fs,
+                     "kernel_seconds": dev_s,
+                     "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[prec],
+                                  "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[prec],
+                                  "peak_unpacked": PEAK_TFLOPS_UNPACKED[prec],
+                                  "frac_unpacked": achieved / PEAK_TFLOPS_UNPACKED[prec],
+                                  "kernel": f"persistent_kernel<{'float' if prec == 'fp32' else 'double'}, neutral>",
+                                  "fp_ops": ops, "coupled_steps": fs, "traffic": None},
                      "one_call_seconds": dt_once,
                      "max_N_l": max(max(r["N"]) for r in out),
                      "min_N_l": min(min(r["N"]) for r in out)}
@@ -539,6 +556,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--integrator", default="BAOAB", choices=["BAOAB", "GL"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="batched: the engine's default options instead of the autotuner's choice")
     ap.add_argument("--plain-schedule", action="store_true",
                     help="single_large: no early top-up (one launch per driver iteration)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -620,7 +639,7 @@ def main():
                           "adaptive": rep}), flush=True)
         return
     if args.workload == "batched":
-        rep = batched_report(ld, args.steps, args.warmup)
+        rep = batched_report(ld, args.steps, args.warmup, autotune=not args.no_autotune)
         print(json.dumps({"metric": "coupled particle-steps/s", "value": rep["fp32"]["coupled_steps_per_s"],
                           "unit": "coupled particle-steps/s", "n_gpus": 1, "steps": args.steps,
                           "warmup": args.warmup, "ms_per_step": 1e3 * rep["fp32"]["seconds"],
@@ -628,7 +647,7 @@ def main():
                           "config": {"workload": "64 estimators: release U[50,950] m, relative eps "
                                                  "log-uniform [1e-3,1e-2], integrator and QoI mixed, "
                                                  "one engine, tiles autotuned"},
-                          "batched": rep}), flush=True)
+                          "roofline": rep["fp32"]["roofline"], "batched": rep}), flush=True)
         return
     cfg = W.single_large(args.integrator)
     L = W.SINGLE_LARGE_LEVELS

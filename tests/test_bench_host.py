@@ -26,7 +26,8 @@ def test_kernel_hash_reads_the_code_object():
 
 
 def test_committed_summaries_carry_a_kernel_hash():
-    for name in ("level_kernel_fp32_single_large_traffic.json", "level_kernel_fp32_single_large_valu.json"):
+    for name in ("level_kernel_fp32_single_large_traffic.json", "level_kernel_fp32_single_large_valu.json",
+                 "level_kernel_fp64_single_large_traffic.json", "level_kernel_fp64_single_large_valu.json"):
         with open(os.path.join(ROOT, "profiles", name)) as f:
             d = json.load(f)
         assert re.fullmatch(r"[0-9a-f]{16}", d["kernel_hash"])
