@@ -13,6 +13,7 @@ import time
 
 import pytest
 
+import oracle
 import paper_1612_07717_amd as ld
 import workloads as W
 
@@ -151,3 +152,24 @@ def test_adaptive_queries_are_served(policy):
     for c, r in zip(cfgs, got):
         e = ld.estimate(1e-2, c, precision="fp32", eps_is_relative=True, N_init=2000, L_max=8)
         assert r["N"] == e["N"] and r["estimate"] == e["estimate"]
+
+
+def test_fp64_served_results_match_the_oracle_driver():
+    """FP64 queries served together (continuous batching) against the oracle's own
+    driver run on each query alone (Sec. 3.3, Sec. 6): the same samples per level and
+    finest level, and estimates within 1e-11 relative."""
+    cfgs = [(W.neutral(300.0, "GL", stream_id=3), 1e-2), (W.neutral(700.0, "BAOAB", stream_id=4), 1e-2),
+            (W.problem(integrator="SE", stream_id=5), 2e-2),
+            (W.neutral(450.0, "BAOAB", qoi="p_above", qa=400.0, r=4, delta=100.0, stream_id=6), 2e-2)]
+    qs = [ld.make_query(c, e, N_init=3000, L_max=9) for c, e in cfgs]
+    with ld.Server(policy="batch", precision="fp64") as srv:
+        tickets = [srv.submit(q) for q in qs]
+        served = [srv.wait(t, timeout=120.0) for t in tickets]
+    for (c, e), got in zip(cfgs, served):
+        assert got is not None
+        r = got[0]
+        o = oracle.estimate(e, c, eps_is_relative=True, N_init=3000, L_max=9)
+        say(f"served fp64 {c['integrator']}: {r['estimate']} N={r['N']} oracle {o['estimate']} N={o['N']}")
+        assert r["N"] == o["N"] and r["L"] == o["L"]
+        assert r["estimate"] == pytest.approx(o["estimate"], rel=1e-11, abs=1e-13)
+
