@@ -292,13 +292,14 @@ def serve_trace(ld, arrivals, policy, precision, n_init, max_seconds=None, drain
             "status_counts": {str(k): v for k, v in sorted(statuses.items())}}
 
 
-def serving_report(ld, rate, duration, seed, n_init, fifo_seconds=None, precisions=("fp32", "fp64")):
+def serving_report(ld, rate, duration, seed, n_init, fifo_seconds=None, precisions=("fp32", "fp64"),
+                   **engine_kw):
     arrivals = W.poisson_arrivals(rate, duration, seed=seed)
     out = {"rate_qps": rate, "duration_s": duration, "arrivals": len(arrivals),
            "eps_range": [3e-4, 1e-2], "N_init": n_init, "max_fine_steps": SERVE_MAX_FINE_STEPS,
            "runs": []}
     for prec in precisions:
-        out["runs"].append(serve_trace(ld, arrivals, "batch", prec, n_init))
+        out["runs"].append(serve_trace(ld, arrivals, "batch", prec, n_init, **engine_kw))
         print(json.dumps({"progress": "serving", **out["runs"][-1]}), file=sys.stderr, flush=True)
     out["runs"].append(serve_trace(ld, arrivals, "fifo", "fp64", n_init, max_seconds=fifo_seconds))
     print(json.dumps({"progress": "serving", **out["runs"][-1]}), file=sys.stderr, flush=True)
@@ -556,6 +557,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--integrator", default="BAOAB", choices=["BAOAB", "GL"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--use-graph", type=int, default=None, choices=[0, 1],
+                    help="serving: capture engine iterations in a HIP graph (default: the engine's default)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="batched: the engine's default options instead of the autotuner's choice")
     ap.add_argument("--plain-schedule", action="store_true",
@@ -583,8 +586,9 @@ def main():
 
     torch.cuda.set_device(0)
     if args.workload == "serving":
+        ekw = {} if args.use_graph is None else {"use_graph": bool(args.use_graph)}
         rep = serving_report(ld, args.rate, args.duration, seed=11, n_init=args.n_init,
-                             fifo_seconds=args.fifo_seconds)
+                             fifo_seconds=args.fifo_seconds, **ekw)
         batch32 = rep["runs"][0]
         print(json.dumps({"metric": "query p50/p99 latency", "value": batch32["p99_ms"],
                           "unit": "ms (p99, FP32 continuous batching)", "n_gpus": 1,

@@ -394,7 +394,9 @@ typedef struct {
     uint64_t pipe_max_samples;    /* wave-specialised tiles for ranges up to this size
                                      (default 131072; 0 disables them) */
     uint32_t pipe_min_steps;      /* ... whose paths have at least this many steps (256) */
-    int32_t use_graph;            /* capture an iteration's launches in a hipGraph (1) */
+    int32_t use_graph;            /* capture an iteration's launches in a hipGraph (default 0:
+                                     direct launches, whose persistent kernels get no more
+                                     blocks than their queues have tiles) */
     void* hip_stream;             /* stream of all engine work (NULL = default) */
 } ld_engine_opts;
 
@@ -437,7 +439,8 @@ int mlmc_estimate_batch(const ld_query* queries, int32_t n, const ld_engine_opts
 
 /* Autotuner: times the batch `queries` on engines with each candidate persistent grid
    (blocks_per_cu in {2, 4, 6, 8, 12, 16}) and tile policy (target_tiles in
-   {4096, 8192, 16384, 32768, 65536}, wave-specialised tiles on/off), keeps the
+   {4096, 8192, 16384, 32768, 65536}, wave-specialised tiles on/off, graph capture
+   on/off), keeps the
    fastest, and writes it to *best (other fields from base). Each candidate gets one
    engine, created outside its timings; reps timings per candidate, the median counts. */
 int ld_engine_autotune(const ld_query* queries, int32_t n, const ld_engine_opts* base,

@@ -503,7 +503,7 @@ def make_query(cfg: dict, eps: float, *, eps_is_relative=True, L_min=2, L_max=20
 
 def engine_opts(*, precision="fp32", max_queries=256, hbm_budget_bytes=1 << 30, blocks_per_cu=8,
                 target_tiles=32768, pipe_max_samples=64 * 2048, pipe_min_steps=256,
-                use_graph=True, stream=None) -> EngineOpts:
+                use_graph=False, stream=None) -> EngineOpts:
     o = EngineOpts()
     load().ld_engine_default_opts(C.byref(o))
     o.precision = PRECISIONS[precision]

@@ -1,14 +1,15 @@
-// engine.cpp -- many MLMC estimates in one persistent launch per iteration.
+// engine.cpp -- many MLMC estimates in one launch per iteration.
 //
 // Each active query owns a slot: its problem parameters and its running level sums
 // (LD_MAX_LEVELS ld_level_sums) live in device memory for the query's lifetime.
 // Submission touches no device: the problem waits in a pinned host table and goes up
 // with the next iteration's tables, and a slot's level sums restart from zero at the
 // merge of its first range. An iteration gathers every query's planned (level, range)
-// pairs, cuts them into tiles with a rule that depends on the range alone, writes the
-// tile and range tables into pinned staging, uploads them (and the new problems) with
-// one copy each, and replays a captured graph: reset queue counters -> persistent
-// kernel per queue (profile kind, or adaptive symplectic Euler) -> merge of each
+// pairs and plans each range's tiles with a rule that depends on the range alone; the
+// range table goes up in one copy (with the new problems), and the device writes the
+// tile table from it, runs the tiles of each queue present (profile kind, or adaptive
+// symplectic Euler) - one block per tile, or persistent blocks taking tiles from the
+// queue's counter when the iteration is a captured graph (use_graph) - and merges each
 // range's partials into the running sums. The running sums of the
 // touched slots come back and each query's planner (mlmc_plan, Sec. 3.3 / Sec. 6)
 // decides its next samples; converged queries leave, new ones are admitted between
@@ -75,8 +76,6 @@ struct ld_engine {
     ld_level_sums* d_partials = nullptr;
     KHeader* h_hdr = nullptr;
     KRange* h_ranges = nullptr;
-    KTile* h_tiles = nullptr;              // pinned tile staging, h_tile_cap tiles (grows)
-    uint64_t h_tile_cap = 0;
     KProblem* h_problems = nullptr;        // pinned copy of every slot's problem
     int32_t new_lo = 0, new_hi = -1;       // slots whose problems await upload
     ld_level_sums* h_running = nullptr;
@@ -122,7 +121,6 @@ void release_resources(ld_engine* e) {
     if (e->d_base) (void)hipFree(e->d_base);
     if (e->h_hdr) (void)hipHostFree(e->h_hdr);
     if (e->h_ranges) (void)hipHostFree(e->h_ranges);
-    if (e->h_tiles) (void)hipHostFree(e->h_tiles);
     if (e->h_problems) (void)hipHostFree(e->h_problems);
     if (e->h_running) (void)hipHostFree(e->h_running);
     if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
@@ -143,60 +141,19 @@ void stream_tiles(const ld_engine* e, const Query& qu, uint64_t n, uint32_t* spl
     *nb = (uint32_t)((n + per * s - 1) / (per * s));
 }
 
-// Tiles of one range, written to out[0..]; the rule depends on the range alone. Returns
-// the number of tiles (tiles_of_range).
-uint64_t tile_range(const ld_engine* e, uint32_t slot, const Query& qu, int32_t level, uint64_t begin,
-                    uint64_t n, uint16_t prio, KTile* out) {
+// How a range is cut into tiles (the rule depends on the range alone): its mode, samples
+// per lane and tile count.
+uint64_t plan_range(const ld_engine* e, const Query& qu, int32_t level, uint64_t n, uint16_t* mode,
+                    uint32_t* spl) {
     const uint64_t M = (uint64_t)qu.prob.M0 << level;
-    KTile t;
-    std::memset(&t, 0, sizeof t);
-    t.slot = slot;
-    t.level = level;
-    t.sample_begin = begin;
-    t.n_samples = n;
-    t.prio = prio;
     if (level >= 1 && n <= e->opts.pipe_max_samples && M >= e->opts.pipe_min_steps && !qu.kp.adaptive) {
-        t.mode = KMODE_PIPE;
-        t.spl = 1;
-        const uint64_t nb = (n + 63) / 64;
-        for (uint64_t b = 0; b < nb; ++b) {
-            t.local_block = (uint32_t)b;
-            out[b] = t;
-        }
-        return nb;
-    }
-    uint32_t spl = 1, nb = 0;
-    stream_tiles(e, qu, n, &spl, &nb);
-    t.mode = KMODE_STREAM;
-    t.spl = spl;
-    for (uint64_t b = 0; b < nb; ++b) {
-        t.local_block = (uint32_t)b;
-        out[b] = t;
-    }
-    return nb;
-}
-
-// Pinned tile staging for at least n tiles. Called only between iterations: the previous
-// iteration's upload from the old buffer has completed (its step synchronised).
-int reserve_tiles(ld_engine* e, uint64_t n) {
-    if (n <= e->h_tile_cap) return LD_OK;
-    uint64_t cap = std::max<uint64_t>(e->h_tile_cap, 4096);
-    while (cap < n) cap *= 2;
-    cap = std::min<uint64_t>(cap, std::max<uint64_t>(e->max_tiles, n));
-    KTile* p = nullptr;
-    if (hipHostMalloc((void**)&p, cap * sizeof(KTile)) != hipSuccess) return fail(LD_ENOMEM, "pinned tile staging failed");
-    if (e->h_tiles) (void)hipHostFree(e->h_tiles);
-    e->h_tiles = p;
-    e->h_tile_cap = cap;
-    return LD_OK;
-}
-
-uint64_t tiles_of_range(const ld_engine* e, const Query& qu, int32_t level, uint64_t n) {
-    const uint64_t M = (uint64_t)qu.prob.M0 << level;
-    if (level >= 1 && n <= e->opts.pipe_max_samples && M >= e->opts.pipe_min_steps && !qu.kp.adaptive)
+        *mode = KMODE_PIPE;
+        *spl = 1;
         return (n + 63) / 64;
-    uint32_t spl = 1, nb = 0;
-    stream_tiles(e, qu, n, &spl, &nb);
+    }
+    uint32_t nb = 0;
+    stream_tiles(e, qu, n, spl, &nb);
+    *mode = KMODE_STREAM;
     return nb;
 }
 
@@ -206,7 +163,8 @@ int capture_graph(ld_engine* e, uint32_t mask) {
     hipGraph_t g = nullptr;
     if (hipStreamBeginCapture(e->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return fail(LD_EDEVICE, "hipStreamBeginCapture failed");
-    int rc = launch_engine_iteration(e->opts.precision, e->grid, mask, e->d_hdr, e->d_tiles, e->d_problems,
+    const uint32_t grids[kNumQueues] = {e->grid, e->grid, e->grid};
+    int rc = launch_engine_iteration(e->opts.precision, true, grids, mask, e->d_hdr, e->d_tiles, e->d_problems,
                                      e->d_partials, e->d_counters, e->d_ranges, e->d_running,
                                      e->d_range_out, e->stream);
     const hipError_t ec = hipStreamEndCapture(e->stream, &g);
@@ -246,7 +204,7 @@ void ld_engine_default_opts(ld_engine_opts* o) {
     o->target_tiles = 32768;
     o->pipe_max_samples = kPipeMaxSamples;
     o->pipe_min_steps = kPipeMinSteps;
-    o->use_graph = 1;
+    o->use_graph = 0;
     o->hip_stream = nullptr;
 }
 
@@ -311,8 +269,7 @@ int ld_engine_create(const ld_engine_opts* opts_in, ld_engine** out) {
     if (hipHostMalloc((void**)&e->h_hdr, sizeof(KHeader)) != hipSuccess ||
         hipHostMalloc((void**)&e->h_ranges, e->max_ranges * sizeof(KRange)) != hipSuccess ||
         hipHostMalloc((void**)&e->h_running, slots * LD_MAX_LEVELS * sizeof(ld_level_sums)) != hipSuccess ||
-        hipHostMalloc((void**)&e->h_problems, slots * sizeof(KProblem)) != hipSuccess ||
-        reserve_tiles(e, std::min<uint64_t>(e->max_tiles, 65536)) != LD_OK) {
+        hipHostMalloc((void**)&e->h_problems, slots * sizeof(KProblem)) != hipSuccess) {
         release_resources(e);
         delete e;
         return fail(LD_ENOMEM, "pinned host staging allocation failed");
@@ -335,6 +292,7 @@ int ld_engine_create(const ld_engine_opts* opts_in, ld_engine** out) {
     }
     e->q.resize(slots);
     if (launch_clear_sums(e->d_running, (uint32_t)(slots * LD_MAX_LEVELS), e->stream) != LD_OK ||
+        launch_reset_counters(e->d_counters, e->stream) != LD_OK ||
         hipStreamSynchronize(e->stream) != hipSuccess) {
         release_resources(e);
         delete e;
@@ -425,7 +383,9 @@ int ld_engine_step(ld_engine* e, int32_t* n_active) {
     uint64_t total = 0;
     for (const Pending& p : pend) {
         const Query& qu = e->q[p.slot];
-        const uint64_t nt = tiles_of_range(e, qu, p.level, p.n);
+        uint16_t mode;
+        uint32_t spl;
+        const uint64_t nt = plan_range(e, qu, p.level, p.n, &mode, &spl);
         if (total + nt > e->max_tiles || taken.size() >= e->max_ranges) continue;
         const int qi = qu.kp.adaptive ? (int)KQUEUE_ADAPT : qu.kp.profile;
         const uint16_t prio = (uint16_t)std::max(0, 3 - (int)std::lround(std::log2(top / steps_of(p))));
@@ -434,10 +394,9 @@ int ld_engine_step(ld_engine* e, int32_t* n_active) {
         total += nt;
     }
     if (total == 0) return fail(LD_ENOMEM, "a single range exceeds the engine's tile budget");
-    int rc = reserve_tiles(e, total);
-    if (rc != LD_OK) return rc;
+    int rc = LD_OK;
     // the queues one after the other in the tile table: neutral, homogeneous, adaptive;
-    // tiles and ranges are written straight into the pinned staging
+    // the ranges go into the pinned staging and the device writes the tiles from them
     const int order[kNumQueues] = {KPROFILE_NEUTRAL, KPROFILE_HOMOGENEOUS, KQUEUE_ADAPT};
     std::memset(e->h_hdr, 0, sizeof(KHeader));
     uint32_t mask = 0;
@@ -456,8 +415,10 @@ int ld_engine_step(ld_engine* e, int32_t* n_active) {
             r.slot = (uint32_t)t.p.slot;
             r.level = t.p.level;
             r.tile_begin = (uint32_t)cursor;
-            r.n_tiles = (uint32_t)tile_range(e, (uint32_t)t.p.slot, qu, t.p.level, t.p.begin, t.p.n, t.prio,
-                                             e->h_tiles + cursor);
+            r.n_tiles = (uint32_t)plan_range(e, qu, t.p.level, t.p.n, &r.mode, &r.spl);
+            r.sample_begin = t.p.begin;
+            r.n_samples = t.p.n;
+            r.prio = t.prio;
             r.fresh = (qu.fresh_levels >> t.p.level) & 1u;
             cursor += r.n_tiles;
             pall.push_back(t.p);
@@ -465,7 +426,7 @@ int ld_engine_step(ld_engine* e, int32_t* n_active) {
         first += count[qi];
     }
     e->h_hdr->n_ranges = nr;
-    // 3. upload (new problems, header, ranges, tiles: one copy each), run, read back
+    // 3. upload (new problems, header, ranges: one copy each), run, read back
     if (e->new_hi >= 0 &&
         hipMemcpyAsync(&e->d_problems[e->new_lo], &e->h_problems[e->new_lo],
                        (size_t)(e->new_hi - e->new_lo + 1) * sizeof(KProblem), hipMemcpyHostToDevice,
@@ -475,8 +436,6 @@ int ld_engine_step(ld_engine* e, int32_t* n_active) {
     e->new_hi = -1;
     if (hipMemcpyAsync(e->d_hdr, e->h_hdr, sizeof(KHeader), hipMemcpyHostToDevice, e->stream) != hipSuccess ||
         hipMemcpyAsync(e->d_ranges, e->h_ranges, nr * sizeof(KRange), hipMemcpyHostToDevice, e->stream) !=
-            hipSuccess ||
-        hipMemcpyAsync(e->d_tiles, e->h_tiles, total * sizeof(KTile), hipMemcpyHostToDevice, e->stream) !=
             hipSuccess)
         return fail(LD_EDEVICE, "uploading the tile tables failed");
     if (e->opts.use_graph && e->graph[mask] == nullptr) {
@@ -488,7 +447,10 @@ int ld_engine_step(ld_engine* e, int32_t* n_active) {
         if (hipGraphLaunch(e->graph[mask], e->stream) != hipSuccess)
             return fail(LD_EDEVICE, "hipGraphLaunch failed");
     } else {
-        rc = launch_engine_iteration(e->opts.precision, e->grid, mask, e->d_hdr, e->d_tiles, e->d_problems,
+        // no captured grid to keep: one block per tile, in tile order
+        uint32_t grids[kNumQueues];
+        for (int qi = 0; qi < kNumQueues; ++qi) grids[qi] = (uint32_t)std::max<uint64_t>(1, count[qi]);
+        rc = launch_engine_iteration(e->opts.precision, false, grids, mask, e->d_hdr, e->d_tiles, e->d_problems,
                                          e->d_partials, e->d_counters, e->d_ranges, e->d_running,
                                          e->d_range_out, e->stream);
         if (rc != LD_OK) return fail(rc, "engine launch failed");
@@ -672,40 +634,43 @@ int ld_engine_autotune(const ld_query* queries, int32_t n, const ld_engine_opts*
     const int32_t grids[] = {2, 4, 6, 8, 12, 16};
     const uint64_t tiles[] = {4096, 8192, 16384, 32768, 65536};
     const uint64_t pipes[] = {0, kPipeMaxSamples};
+    const int32_t graphs[] = {0, 1};
     std::vector<ld_estimate_result> res(n);
     double best_t = 1e300;
     ld_engine_opts best_o = b;
     reps = std::max(1, reps);
     for (int32_t g : grids)
         for (uint64_t t : tiles)
-            for (uint64_t pm : pipes) {
-                ld_engine_opts o = b;
-                o.blocks_per_cu = g;
-                o.target_tiles = t;
-                o.pipe_max_samples = pm;
-                // one engine per configuration, so that its allocation stays out of the
-                // timings (as for a server, which keeps its engine)
-                ld_engine* e = nullptr;
-                int rc = ld_engine_create(&o, &e);
-                if (rc != LD_OK) return rc;
-                std::vector<double> times;
-                for (int32_t r = 0; r < reps; ++r) {
-                    const double t0 = now_seconds();
-                    rc = run_to_completion(e, queries, n, res.data());
-                    if (rc < 0 && rc != LD_ENONFINITE) {
-                        ld_engine_destroy(e);
-                        return rc;
+            for (uint64_t pm : pipes)
+                for (int32_t ug : graphs) {
+                    ld_engine_opts o = b;
+                    o.blocks_per_cu = g;
+                    o.target_tiles = t;
+                    o.pipe_max_samples = pm;
+                    o.use_graph = ug;
+                    // one engine per configuration, so that its allocation stays out of the
+                    // timings (as for a server, which keeps its engine)
+                    ld_engine* e = nullptr;
+                    int rc = ld_engine_create(&o, &e);
+                    if (rc != LD_OK) return rc;
+                    std::vector<double> times;
+                    for (int32_t r = 0; r < reps; ++r) {
+                        const double t0 = now_seconds();
+                        rc = run_to_completion(e, queries, n, res.data());
+                        if (rc < 0 && rc != LD_ENONFINITE) {
+                            ld_engine_destroy(e);
+                            return rc;
+                        }
+                        times.push_back(now_seconds() - t0);
                     }
-                    times.push_back(now_seconds() - t0);
+                    ld_engine_destroy(e);
+                    std::sort(times.begin(), times.end());
+                    const double med = times[times.size() / 2];
+                    if (med < best_t) {
+                        best_t = med;
+                        best_o = o;
+                    }
                 }
-                ld_engine_destroy(e);
-                std::sort(times.begin(), times.end());
-                const double med = times[times.size() / 2];
-                if (med < best_t) {
-                    best_t = med;
-                    best_o = o;
-                }
-            }
     *best = best_o;
     if (best_seconds) *best_seconds = best_t;
     return LD_OK;

@@ -568,6 +568,47 @@ __global__ __launch_bounds__(kBlock, 3) void level_kernel(const KArgs args,
 // ADAPT: the queue of adaptive symplectic Euler tiles (neutral profile), each run as the
 // level kernel runs that block, with 32- or 64-bit tick counters as its level needs.
 // ---------------------------------------------------------------------------------
+// One tile of a queue: its block of samples in the tile's mode, the block's sums written
+// to the tile's partial. Both engine kernels below run tiles with this code, so a tile's
+// partial does not depend on which of them ran it.
+template <typename R, int PROF, bool ADAPT>
+__device__ __forceinline__ void run_tile(const KQueue& q, uint32_t t, const KTile* __restrict__ tiles,
+                                         const KProblem* __restrict__ problems,
+                                         ld_level_sums* __restrict__ partials, PipeLds<R>& lds) {
+    const KTile tile = tiles[q.first + t];
+    const KProblem& kp = problems[tile.slot];
+    KItem item;
+    item.level = tile.level;
+    item.spl = tile.spl;
+    item.block_begin = 0;
+    item.n_blocks = 0;
+    item.sample_begin = tile.sample_begin;
+    item.n_samples = tile.n_samples;
+    item.out_slot = 0;
+    item.mode = tile.mode;
+    item.prio = tile.prio;
+    set_priority(tile.prio);
+    Acc acc;
+    acc_zero(acc);
+    if constexpr (ADAPT) {
+        if (((uint64_t)kp.M0 << (tile.level + kAdaptTickBits)) + ((uint64_t)2 << kAdaptTickBits) <
+            ((uint64_t)1 << 32))
+            run_block<R, KINTEG_SE_ADAPT, PROF>(kp, item, tile.local_block, acc, nullptr, lds);
+        else
+            run_block<R, KINTEG_SE_ADAPT_WIDE, PROF>(kp, item, tile.local_block, acc, nullptr, lds);
+    } else {
+        switch (kp.integ) {
+            case KINTEG_SE: run_block<R, KINTEG_SE, PROF>(kp, item, tile.local_block, acc, nullptr, lds); break;
+            case KINTEG_GL: run_block<R, KINTEG_GL, PROF>(kp, item, tile.local_block, acc, nullptr, lds); break;
+            default: run_block<R, KINTEG_BAOAB, PROF>(kp, item, tile.local_block, acc, nullptr, lds); break;
+        }
+    }
+    block_reduce_all(acc);
+    if (wave_index() == 0) store_sums(&partials[q.first + t], acc);   // same values from every lane
+}
+
+// Persistent form (a fixed grid, as a captured graph needs): blocks take tiles from the
+// queue's counter until it is empty.
 template <typename R, int PROF, bool ADAPT = false>
 __global__ __launch_bounds__(kBlock) void persistent_kernel(const KHeader* __restrict__ hdr,
                                                             const KTile* __restrict__ tiles,
@@ -592,36 +633,44 @@ __global__ __launch_bounds__(kBlock) void persistent_kernel(const KHeader* __res
         const uint32_t t = __builtin_amdgcn_readfirstlane(sh_tile);
         __syncthreads();
         if (t >= q.n_tiles) break;
-        const KTile tile = tiles[q.first + t];
-        const KProblem& kp = problems[tile.slot];
-        KItem item;
-        item.level = tile.level;
-        item.spl = tile.spl;
-        item.block_begin = 0;
-        item.n_blocks = 0;
-        item.sample_begin = tile.sample_begin;
-        item.n_samples = tile.n_samples;
-        item.out_slot = 0;
-        item.mode = tile.mode;
-        item.prio = tile.prio;
-        set_priority(tile.prio);
-        Acc acc;
-        acc_zero(acc);
-        if constexpr (ADAPT) {
-            if (((uint64_t)kp.M0 << (tile.level + kAdaptTickBits)) + ((uint64_t)2 << kAdaptTickBits) <
-                ((uint64_t)1 << 32))
-                run_block<R, KINTEG_SE_ADAPT, PROF>(kp, item, tile.local_block, acc, nullptr, lds);
-            else
-                run_block<R, KINTEG_SE_ADAPT_WIDE, PROF>(kp, item, tile.local_block, acc, nullptr, lds);
-        } else {
-            switch (kp.integ) {
-                case KINTEG_SE: run_block<R, KINTEG_SE, PROF>(kp, item, tile.local_block, acc, nullptr, lds); break;
-                case KINTEG_GL: run_block<R, KINTEG_GL, PROF>(kp, item, tile.local_block, acc, nullptr, lds); break;
-                default: run_block<R, KINTEG_BAOAB, PROF>(kp, item, tile.local_block, acc, nullptr, lds); break;
-            }
+        run_tile<R, PROF, ADAPT>(q, t, tiles, problems, partials, lds);
+    }
+}
+
+// One block per tile (a grid of exactly the queue's tile count): blocks start in tile
+// order, so the longest paths, first in the table, start first.
+template <typename R, int PROF, bool ADAPT = false>
+__global__ __launch_bounds__(kBlock) void tile_kernel(const KHeader* __restrict__ hdr,
+                                                      const KTile* __restrict__ tiles,
+                                                      const KProblem* __restrict__ problems,
+                                                      ld_level_sums* __restrict__ partials) {
+    __shared__ PipeLds<R> lds;
+    const KQueue q = hdr->queue[ADAPT ? (int)KQUEUE_ADAPT : PROF];
+    const uint32_t t = blockIdx.x;
+    if (t >= q.n_tiles) return;
+    run_tile<R, PROF, ADAPT>(q, t, tiles, problems, partials, lds);
+}
+
+// The tile table of an iteration from its ranges: tile b of a range is block b of it.
+__global__ __launch_bounds__(kBlock) void expand_tiles_kernel(const KHeader* __restrict__ hdr,
+                                                              const KRange* __restrict__ ranges,
+                                                              KTile* __restrict__ tiles) {
+    const uint32_t n_ranges = hdr->n_ranges;
+    for (uint32_t r = blockIdx.x; r < n_ranges; r += gridDim.x) {
+        const KRange rg = ranges[r];
+        KTile t;
+        t.slot = rg.slot;
+        t.level = rg.level;
+        t.sample_begin = rg.sample_begin;
+        t.n_samples = rg.n_samples;
+        t.spl = rg.spl;
+        t.mode = rg.mode;
+        t.prio = rg.prio;
+        t.pad = 0;
+        for (uint32_t b = threadIdx.x; b < rg.n_tiles; b += kBlock) {
+            t.local_block = b;
+            tiles[rg.tile_begin + b] = t;
         }
-        block_reduce_all(acc);
-        if (wave == 0) store_sums(&partials[q.first + t], acc);   // same values from every lane
     }
 }
 
@@ -630,12 +679,16 @@ __global__ void reset_counters_kernel(uint32_t* counters, int n) {
 }
 
 // Each range's tile partials, in tile order, are reduced and added to the running sums
-// of (query slot, level); also written per range for the caller.
+// of (query slot, level); also written per range for the caller. The persistent kernels
+// of the iteration have ended (stream order), so block 0 also sets the queue counters
+// back to zero for the next iteration.
 __global__ __launch_bounds__(kBlock) void merge_ranges_kernel(const KHeader* __restrict__ hdr,
                                                               const KRange* __restrict__ ranges,
                                                               const ld_level_sums* __restrict__ partials,
                                                               ld_level_sums* __restrict__ running,
-                                                              ld_level_sums* __restrict__ range_out) {
+                                                              ld_level_sums* __restrict__ range_out,
+                                                              uint32_t* __restrict__ counters) {
+    if (blockIdx.x == 0 && threadIdx.x < (unsigned)kNumQueues) counters[threadIdx.x] = 0u;
     const uint32_t n_ranges = hdr->n_ranges;
     for (uint32_t r = blockIdx.x; r < n_ranges; r += gridDim.x) {
         const KRange rg = ranges[r];
@@ -853,39 +906,53 @@ int launch_levels(const KArgs& args, uint32_t total_blocks, ld_level_sums* d_par
     return LD_OK;
 }
 
-int launch_engine_iteration(int precision, uint32_t grid_blocks, uint32_t queue_mask,
+template <typename R, int PROF, bool ADAPT>
+void launch_queue(bool persistent, uint32_t grid, hipStream_t s, const KHeader* d_hdr, const KTile* d_tiles,
+                  const KProblem* d_problems, ld_level_sums* d_partials, uint32_t* d_counters) {
+    if (persistent)
+        hipLaunchKernelGGL((persistent_kernel<R, PROF, ADAPT>), dim3(grid), dim3(kBlock), 0, s, d_hdr, d_tiles,
+                           d_problems, d_partials, d_counters);
+    else
+        hipLaunchKernelGGL((tile_kernel<R, PROF, ADAPT>), dim3(grid), dim3(kBlock), 0, s, d_hdr, d_tiles,
+                           d_problems, d_partials);
+}
+
+template <typename R>
+void launch_queues(bool persistent, const uint32_t* grid, uint32_t mask, hipStream_t s, const KHeader* d_hdr,
+                   const KTile* d_tiles, const KProblem* d_problems, ld_level_sums* d_partials,
+                   uint32_t* d_counters) {
+    if ((mask >> KPROFILE_NEUTRAL) & 1u)
+        launch_queue<R, KPROFILE_NEUTRAL, false>(persistent, grid[KPROFILE_NEUTRAL], s, d_hdr, d_tiles, d_problems,
+                                                 d_partials, d_counters);
+    if ((mask >> KPROFILE_HOMOGENEOUS) & 1u)
+        launch_queue<R, KPROFILE_HOMOGENEOUS, false>(persistent, grid[KPROFILE_HOMOGENEOUS], s, d_hdr, d_tiles,
+                                                     d_problems, d_partials, d_counters);
+    if ((mask >> KQUEUE_ADAPT) & 1u)
+        launch_queue<R, KPROFILE_NEUTRAL, true>(persistent, grid[KQUEUE_ADAPT], s, d_hdr, d_tiles, d_problems,
+                                                d_partials, d_counters);
+}
+
+int launch_engine_iteration(int precision, bool persistent, const uint32_t* grid_blocks, uint32_t queue_mask,
                             const KHeader* d_hdr, const KTile* d_tiles, const KProblem* d_problems,
                             ld_level_sums* d_partials, uint32_t* d_counters,
                             const KRange* d_ranges, ld_level_sums* d_running,
                             ld_level_sums* d_range_out, void* stream) {
     hipStream_t s = (hipStream_t)stream;
-    const bool neutral = (queue_mask >> KPROFILE_NEUTRAL) & 1u;
-    const bool homogeneous = (queue_mask >> KPROFILE_HOMOGENEOUS) & 1u;
-    const bool adapt = (queue_mask >> KQUEUE_ADAPT) & 1u;
-    hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, s, d_counters, (int)kNumQueues);
-    if (precision == LD_FP32) {
-        if (neutral)
-            hipLaunchKernelGGL((persistent_kernel<float, KPROFILE_NEUTRAL>), dim3(grid_blocks), dim3(kBlock), 0,
-                               s, d_hdr, d_tiles, d_problems, d_partials, d_counters);
-        if (homogeneous)
-            hipLaunchKernelGGL((persistent_kernel<float, KPROFILE_HOMOGENEOUS>), dim3(grid_blocks), dim3(kBlock),
-                               0, s, d_hdr, d_tiles, d_problems, d_partials, d_counters);
-        if (adapt)
-            hipLaunchKernelGGL((persistent_kernel<float, KPROFILE_NEUTRAL, true>), dim3(grid_blocks),
-                               dim3(kBlock), 0, s, d_hdr, d_tiles, d_problems, d_partials, d_counters);
-    } else {
-        if (neutral)
-            hipLaunchKernelGGL((persistent_kernel<double, KPROFILE_NEUTRAL>), dim3(grid_blocks), dim3(kBlock), 0,
-                               s, d_hdr, d_tiles, d_problems, d_partials, d_counters);
-        if (homogeneous)
-            hipLaunchKernelGGL((persistent_kernel<double, KPROFILE_HOMOGENEOUS>), dim3(grid_blocks), dim3(kBlock),
-                               0, s, d_hdr, d_tiles, d_problems, d_partials, d_counters);
-        if (adapt)
-            hipLaunchKernelGGL((persistent_kernel<double, KPROFILE_NEUTRAL, true>), dim3(grid_blocks),
-                               dim3(kBlock), 0, s, d_hdr, d_tiles, d_problems, d_partials, d_counters);
-    }
+    hipLaunchKernelGGL(expand_tiles_kernel, dim3(kMergeGrid), dim3(kBlock), 0, s, d_hdr, d_ranges,
+                       (KTile*)d_tiles);
+    if (precision == LD_FP32)
+        launch_queues<float>(persistent, grid_blocks, queue_mask, s, d_hdr, d_tiles, d_problems, d_partials,
+                             d_counters);
+    else
+        launch_queues<double>(persistent, grid_blocks, queue_mask, s, d_hdr, d_tiles, d_problems, d_partials,
+                              d_counters);
     hipLaunchKernelGGL(merge_ranges_kernel, dim3(kMergeGrid), dim3(kBlock), 0, s, d_hdr, d_ranges, d_partials,
-                       d_running, d_range_out);
+                       d_running, d_range_out, d_counters);
+    return hipGetLastError() == hipSuccess ? LD_OK : LD_EDEVICE;
+}
+
+int launch_reset_counters(uint32_t* d_counters, void* stream) {
+    hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, (hipStream_t)stream, d_counters, (int)kNumQueues);
     return hipGetLastError() == hipSuccess ? LD_OK : LD_EDEVICE;
 }
 

@@ -111,24 +111,36 @@ struct KHeader {
     uint32_t pad[3];
 };
 
-// A range's tiles are contiguous: partials [tile_begin, tile_begin + n_tiles). fresh:
-// the first range of this (slot, level) since the slot was taken, so its running sums
-// start from zero (whatever an earlier query left there).
+// A range of an engine iteration: samples [sample_begin, sample_begin + n_samples) of
+// (slot, level), cut into n_tiles tiles of one mode (spl samples per lane in STREAM
+// tiles) at tiles [tile_begin, tile_begin + n_tiles) of the tile table, whose partials
+// are contiguous alike; the device writes the tiles from the range. fresh: the first
+// range of this (slot, level) since the slot was taken, so its running sums start from
+// zero (whatever an earlier query left there).
 struct KRange {
     uint32_t slot;
     int32_t level;
     uint32_t tile_begin;
     uint32_t n_tiles;
+    uint64_t sample_begin;
+    uint64_t n_samples;
+    uint32_t spl;
+    uint16_t mode;
+    uint16_t prio;
     uint32_t fresh;
-    uint32_t pad[3];
+    uint32_t pad;
 };
 
 constexpr int kMergeGrid = 256;   // blocks of the range-merge kernel (grid-stride)
 
-// Enqueues one engine iteration: reset the queue counters, the persistent kernel of
-// each queue whose bit (1 << KPROFILE_*, 1 << KQUEUE_ADAPT) is set in queue_mask, then
-// the range merge into the running sums.
-int launch_engine_iteration(int precision, uint32_t grid_blocks, uint32_t queue_mask,
+// Enqueues one engine iteration: the tile table written from the ranges, then for each
+// queue whose bit (1 << KPROFILE_*,
+// 1 << KQUEUE_ADAPT) is set in queue_mask, its tiles in grid_blocks[queue] blocks, either
+// persistent ones that take tiles from the queue's counter (a fixed grid, for captured
+// graphs) or one block per tile (grid_blocks[queue] = its tile count); then the range
+// merge into the running sums, which also sets the queue counters back to zero (they
+// must be zero when an iteration starts).
+int launch_engine_iteration(int precision, bool persistent, const uint32_t* grid_blocks, uint32_t queue_mask,
                             const KHeader* d_hdr, const KTile* d_tiles, const KProblem* d_problems,
                             ld_level_sums* d_partials, uint32_t* d_counters,
                             const KRange* d_ranges, ld_level_sums* d_running,
@@ -150,5 +162,7 @@ int launch_pdf_bins(const KBins& bins, const KProblem& kp, const double* d_dump,
                     ld_level_sums* d_partials, ld_level_sums* d_out, void* stream);
 
 int launch_clear_sums(ld_level_sums* d_sums, uint32_t n, void* stream);
+// Sets the engine's queue counters to zero (once, when the engine is made).
+int launch_reset_counters(uint32_t* d_counters, void* stream);
 
 }  // namespace ldm

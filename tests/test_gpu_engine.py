@@ -77,7 +77,7 @@ def test_admission_release_and_graph_equivalence():
     cfgs = _mixed_configs(7, seed=9)
     qs = [_query(c, e, rel, N_init=2000, L_max=10) for c, e, rel in cfgs]
     ref = ld.estimate_batch(qs, precision="fp32", use_graph=False)
-    with ld.Engine(precision="fp32", max_queries=3) as eng:
+    with ld.Engine(precision="fp32", max_queries=3, use_graph=True) as eng:   # graph-captured iterations
         handles = [eng.submit(q) for q in qs[:3]]
         assert all(h is not None for h in handles)
         assert eng.submit(qs[3]) is None                 # LD_EBUSY: no slot
