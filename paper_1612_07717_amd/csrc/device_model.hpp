@@ -239,14 +239,15 @@ __device__ __forceinline__ void o_coeffs(const Consts<R>& c, R x, R h, R& su, R&
     }
 }
 
-// o_coeffs and the drift coefficients a, b at X (one square root of H - X_c serves both).
+// o_coeffs and the drift coefficients of a step of length h at X, a h and b h (one square
+// root of H - X_c serves both; a, b as in drift_at).
 template <typename R, int PROF>
-__device__ __forceinline__ void coeffs_at(const Consts<R>& c, R x, R h, R& su, R& z, R& a, R& b) {
+__device__ __forceinline__ void coeffs_at(const Consts<R>& c, R x, R h, R& su, R& z, R& ah, R& bh) {
     if (PROF == KPROFILE_HOMOGENEOUS) {
         su = c.su_h;
         z = -c.lam_h * h;
-        a = (R)0;
-        b = (R)0;
+        ah = (R)0;
+        bh = (R)0;
     } else {
         const R xc = Math<R>::clamp_(x, c.eps, c.Hme);
         const R d = c.H - xc;
@@ -255,24 +256,26 @@ __device__ __forceinline__ void coeffs_at(const Consts<R>& c, R x, R h, R& su, R
         const R r = Math<R>::sqrt_(d * sqd);
         su = c.ksH * r;
         z = r * ((-c.kl * h) * Math<R>::rcp(xc));
-        // inside [eps_reg, H - eps_reg] exactly when the cut-off leaves X as it is (one
-        // vector compare; no scalar combination of two)
+        // inside [eps_reg, H - eps_reg] exactly when the cut-off leaves X as it is
         const bool inside = xc == x;
-        a = inside ? c.acoef_h * sqd : (R)0;
-        b = inside ? (R)0.75 * invd : (R)0;
+        ah = inside ? (c.acoef_h * h) * sqd : (R)0;
+        bh = inside ? ((R)0.75 * h) * invd : (R)0;
     }
 }
 
 // The drift coefficients of a B half-step of length hh at X: a hh and b hh, with
 // a = (3/4)(kappa_sigma u_*)^2 sqrt(H - X) / H^(3/2) and b = (3/4) / (H - X) inside
 // [eps_reg, H - eps_reg], 0 outside. The half-step is then U - a hh - (b hh) U^2.
-template <typename R, int PROF>
+// ONE_CMP: the inside test as one vector compare against the cut-off position (no scalar
+// combination of two compares waits on the path's chain); otherwise two compares. Both
+// give the same answer.
+template <typename R, int PROF, bool ONE_CMP = false>
 __device__ __forceinline__ void drift_at(const Consts<R>& c, R x, R hh, R& ah, R& bh) {
     if (PROF == KPROFILE_HOMOGENEOUS) {
         ah = (R)0;
         bh = (R)0;
     } else {
-        const bool inside = Math<R>::clamp_(x, c.eps, c.Hme) == x;
+        const bool inside = ONE_CMP ? Math<R>::clamp_(x, c.eps, c.Hme) == x : (x >= c.eps) && (x <= c.Hme);
         R sq, inv;
         Math<R>::sqrt_and_rcp(c.H - x, sq, inv);
         ah = inside ? (c.acoef_h * hh) * sq : (R)0;
@@ -382,26 +385,27 @@ template <typename R, int INTEG, int PROF, bool COARSE, int TIER, int FOLD>
 __device__ __forceinline__ void step_impl(const Consts<R>& c, Path<R>& p, R h, R hh, R xi,
                                           R& tilde, R& w, uint32_t& key) {
     if (INTEG == KINTEG_SE) {                                        // Eq. (8)
-        R su, z, a, b;                                               // z = -lambda h
-        coeffs_at<R, PROF>(c, p.x, h, su, z, a, b);
+        R su, z, ah, bh;                                             // z = -lambda h
+        coeffs_at<R, PROF>(c, p.x, h, su, z, ah, bh);
         const R noise = COARSE ? Math<R>::flip(xi, p.sgn) : xi;
         if (!COARSE) tilde = Math<R>::flip(xi, p.sgn);
         const R amp = su * Math<R>::sqrt_((R)-2 * z);                  // sigma sqrt(h)
-        const R drift = -(a + b * p.u * p.u);
-        p.u = ((R)1 + z) * p.u + drift * h + amp * noise;
+        const R u0 = p.u;
+        const R lin = ((R)1 + z) * u0 - ah;                          // (1 - lambda h) U - a h
+        p.u = Math<R>::fma_(amp, noise, lin - (bh * u0) * u0);       // - b h U^2 + sigma dW
         p.x = p.x + p.u * h;
         fold_or_track<R, FOLD>(p, c.H, key);
         w = (R)1;
     } else if (INTEG == KINTEG_GL) {                                 // Eq. (9)
-        R su, z, a, b;
-        coeffs_at<R, PROF>(c, p.x, h, su, z, a, b);
+        R su, z, ah, bh;
+        coeffs_at<R, PROF>(c, p.x, h, su, z, ah, bh);
         const R noise = COARSE ? Math<R>::flip(xi, p.sgn) : xi;
         if (!COARSE) tilde = Math<R>::flip(xi, p.sgn);
         const R e1 = o_step_expm1<R, TIER>(z);
         w = (R)1 + e1;
         const R sn = su * noise;
         const R us = Math<R>::fma_(sn, Math<R>::sqrt_(-e1 * ((R)2 + e1)), w * p.u);   // O
-        p.u = kick(us, a * h, b * h);                                // B at (X_n, U*)
+        p.u = kick(us, ah, bh);                                      // B at (X_n, U*)
         p.x = p.x + p.u * h;                                         // A
         fold_or_track<R, FOLD>(p, c.H, key);
     } else {                                                         // Eq. (10)
@@ -418,7 +422,7 @@ __device__ __forceinline__ void step_impl(const Consts<R>& c, Path<R>& p, R h, R
         p.u = Math<R>::fma_(sn, Math<R>::sqrt_(-e1 * ((R)2 + e1)), w * p.u);   // O at X_{n+1/2}
         p.x = p.x + p.u * hh;                                        // A
         fold_or_track<R, FOLD>(p, c.H, key);
-        drift_at<R, PROF>(c, p.x, hh, p.a, p.b);
+        drift_at<R, PROF, FOLD == FOLD_TRACK>(c, p.x, hh, p.a, p.b);
         p.u = kick(p.u, p.a, p.b);                                   // B at (X_{n+1}, U*)
     }
 }
