@@ -514,7 +514,8 @@ def batched_report(ld, steps, warmup, autotune=True):
                                   "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[prec],
                                   "peak_unpacked": PEAK_TFLOPS_UNPACKED[prec],
                                   "frac_unpacked": achieved / PEAK_TFLOPS_UNPACKED[prec],
-                                  "kernel": f"persistent_kernel<{'float' if prec == 'fp32' else 'double'}, neutral>",
+                                  "kernel": ("persistent_kernel" if o.use_graph else "tile_kernel")
+                                            + f"<{'float' if prec == 'fp32' else 'double'}, neutral>",
                                   "fp_ops": ops, "coupled_steps": fs, "traffic": None},
                      "one_call_seconds": dt_once,
                      "max_N_l": max(max(r["N"]) for r in out),
