@@ -55,8 +55,17 @@ extern "C" {
 #define LD_ENONFINITE (-5)       /* some samples were non-finite (excluded from the sums)    */
 #define LD_ENODEVICE (-6)        /* no usable gfx950 device                                 */
 
-typedef enum { LD_SE = 0, LD_GL = 1, LD_BAOAB = 2 } ld_integrator;   /* Eqs. 8, 9, 10 */
-typedef enum { LD_FP64 = 0, LD_FP32 = 1 } ld_precision;              /* path arithmetic */
+/* In C++ the typed enums below have int as their fixed underlying type, so that every
+   int a C caller passes is a value of the type; the library rejects unknown values with
+   LD_EINVAL. The C ABI is the same either way (an int argument). */
+#ifdef __cplusplus
+#define LD_ENUM_BASE : int
+#else
+#define LD_ENUM_BASE
+#endif
+
+typedef enum LD_ENUM_BASE { LD_SE = 0, LD_GL = 1, LD_BAOAB = 2 } ld_integrator;   /* Eqs. 8, 9, 10 */
+typedef enum LD_ENUM_BASE { LD_FP64 = 0, LD_FP32 = 1 } ld_precision;              /* path arithmetic */
 
 enum { LD_PROFILE_HOMOGENEOUS = 0, LD_PROFILE_NEUTRAL_BL = 1 };
 enum { LD_RELEASE_FIXED_W = 0, LD_RELEASE_GAUSSIAN_W = 1, LD_RELEASE_WELL_MIXED = 2 };
@@ -333,7 +342,7 @@ typedef struct {
 
 int mlmc_plan_pdf(const ld_pdf_plan_in* in, ld_pdf_plan_out* out);
 
-typedef enum { LD_MLMC = 0, LD_STMC = 1 } ld_estimator;
+typedef enum LD_ENUM_BASE { LD_MLMC = 0, LD_STMC = 1 } ld_estimator;
 
 typedef struct {
     double estimate[LD_MAX_BINS];   /* E[P_i(X_T)] per bin */

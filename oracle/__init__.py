@@ -28,10 +28,11 @@ COUPLINGS = {"reflected": 0, "naive": 1}
 MAX_LEVELS = 32
 
 
-def build(src: str = _SRC, out: str = _DEFAULT_LIB) -> str:
-    """Compile liboracle.so with gcc (FP64, no fast-math, no FMA contraction)."""
+def build(src: str = _SRC, out: str = _DEFAULT_LIB, extra_flags=()) -> str:
+    """Compile liboracle.so with gcc (FP64, no fast-math, no FMA contraction).
+    `extra_flags` go to gcc as they are (a sanitizer build passes its options here)."""
     cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared",
-           "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra",
+           "-ffp-contract=off", "-fno-fast-math", "-Wall", "-Wextra", *extra_flags,
            "-I", _HERE, "-o", out + ".tmp", src, "-lm"]
     subprocess.run(cmd, check=True, cwd=_HERE)
     os.replace(out + ".tmp", out)

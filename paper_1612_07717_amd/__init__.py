@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libldmlmc.so")
+# A run that checks the host code under sanitizers points this at its own build.
+LIB_PATH = os.environ.get("LDMLMC_LIB", os.path.join(HERE, "libldmlmc.so"))
 MAX_LEVELS = 32
 
 LD_OK, LD_WARN_NOT_CONVERGED = 0, 1

@@ -31,10 +31,13 @@ def hipcc() -> str:
     return "hipcc"
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, out: str = LIB, host_flags=()) -> str:
+    """Compile every source into one shared library at `out`. Each of `host_flags` is
+    passed to the host compilation only (behind -Xarch_host); device code is unchanged."""
     srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"), "-o", tmp] + srcs
+    tmp = out + ".tmp"
+    host = [a for f in host_flags for a in ("-Xarch_host", f)]
+    cmd = [hipcc()] + HIPCC_FLAGS + host + ["-I", os.path.join(ROOT, "include"), "-o", tmp] + srcs
     r = subprocess.run(cmd, capture_output=True, text=True)
     msgs = [ln for ln in (r.stdout + r.stderr).splitlines()
             if "packed-fp32-ops' is not a recognized feature" not in ln]
@@ -42,8 +45,8 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError("hipcc failed:\n" + "\n".join(msgs))
     if verbose and msgs:
         print("\n".join(msgs), file=sys.stderr)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

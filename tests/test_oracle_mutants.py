@@ -84,9 +84,11 @@ MUTANTS = [
      "oracle_profile(p, 0.0, &su, &tau);\n            oracle_normals"),
 ]
 
-PIN_FILES = ["test_oracle_rng.py", "test_oracle_philox_independent.py", "test_oracle_model.py", "test_oracle_closed_forms.py",
-             "test_oracle_coupling.py", "test_oracle_smoothing_sums_driver.py",
-             "test_oracle_paper_values.py", "test_oracle_adaptive.py"]
+# Fast files first: a run stops at its first failing pin.
+PIN_FILES = ["test_oracle_rng.py", "test_oracle_philox_independent.py", "test_oracle_model.py",
+             "test_oracle_closed_forms.py", "test_oracle_adaptive.py",
+             "test_oracle_smoothing_sums_driver.py", "test_oracle_paper_values.py",
+             "test_oracle_coupling.py"]
 
 
 def _run_mutant(args):
@@ -101,7 +103,7 @@ def _run_mutant(args):
     with open(csrc, "w") as f:
         f.write(mutated)
     oracle.build(src=csrc, out=lib)
-    env = dict(os.environ, LD_ORACLE_LIB=lib, OMP_NUM_THREADS="2")
+    env = dict(os.environ, LD_ORACLE_LIB=lib, OMP_NUM_THREADS="1")
     cmd = [sys.executable, "-m", "pytest", "-x", "-q", "-m", "not slow and not gpu",
            "-p", "no:cacheprovider"] + [os.path.join(ROOT, "tests", f) for f in PIN_FILES]
     r = subprocess.run(cmd, env=env, cwd=ROOT, capture_output=True, text=True, timeout=900)
@@ -111,7 +113,7 @@ def _run_mutant(args):
 @pytest.mark.slow
 def test_every_planted_mistake_fails_a_pin():
     with tempfile.TemporaryDirectory() as tmp:
-        with ThreadPoolExecutor(max_workers=4) as pool:
+        with ThreadPoolExecutor(max_workers=max(2, min(8, os.cpu_count() or 2))) as pool:
             results = list(pool.map(_run_mutant, [(n, o, w, tmp) for n, o, w in MUTANTS]))
     survivors = [(n, out) for n, rc, out in results if rc == 0]
     assert not survivors, "mistakes no pin caught: " + "; ".join(n for n, _ in survivors)
