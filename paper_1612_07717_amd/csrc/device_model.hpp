@@ -197,6 +197,8 @@ struct Consts {
     R kl;                       // ksH / kappa_tau: lambda = kl (H - X)^(3/4) / X
     R acoef_h;                  // (3/4) (kappa_sigma u_*)^2 / H^(3/2)
     R su_h, lam_h;              // homogeneous sigma_U and lambda
+    R sxi;                      // scale of the normals the steps take (sigma_U = sxi sr):
+                                // ksH in the neutral layer, sigma_U when homogeneous
 };
 
 template <typename R>
@@ -210,6 +212,7 @@ __device__ __forceinline__ Consts<R> make_consts(const KProblem& p) {
     c.acoef_h = (R)(0.75 * p.ks * p.ks / (p.H * sqrt(p.H)));
     c.su_h = (R)p.sigma_u;
     c.lam_h = (R)(1.0 / p.tau);
+    c.sxi = (R)(p.profile == KPROFILE_HOMOGENEOUS ? p.sigma_u : p.ksH);
     return c;
 }
 
@@ -221,20 +224,21 @@ __device__ __forceinline__ R sigma_at(const Consts<R>& c, R x) {
     return c.ksH * Math<R>::sqrt_(d * Math<R>::sqrt_(d));
 }
 
-// O-step coefficients at X for step size h: sigma_U and z = -lambda h, lambda = 1/tau =
-// sigma_U / (kappa_tau X_c) (Eqs. 5, 7). With r = (H - X_c)^(3/4) both are one multiply
-// from r: sigma_U = ksH r, z = r (-kl h / X_c); -kl h is the same for every step of a
-// path and 1/X_c is computed beside r.
+// O-step coefficients at X for step size h: sr = sigma_U / sxi and z = -lambda h, lambda =
+// 1/tau = sigma_U / (kappa_tau X_c) (Eqs. 5, 7). In the neutral layer sr is
+// r = (H - X_c)^(3/4) itself (sigma_U = ksH r, and the normals come scaled by ksH) and
+// z = r (-kl h / X_c), one multiply from r: -kl h is the same for every step of a path
+// and 1/X_c is computed beside r. Homogeneous: sr = 1.
 template <typename R, int PROF>
-__device__ __forceinline__ void o_coeffs(const Consts<R>& c, R x, R h, R& su, R& z) {
+__device__ __forceinline__ void o_coeffs(const Consts<R>& c, R x, R h, R& sr, R& z) {
     if (PROF == KPROFILE_HOMOGENEOUS) {
-        su = c.su_h;
+        sr = (R)1;
         z = -c.lam_h * h;
     } else {
         const R xc = Math<R>::clamp_(x, c.eps, c.Hme);
         const R d = c.H - xc;
         const R r = Math<R>::sqrt_(d * Math<R>::sqrt_(d));
-        su = c.ksH * r;
+        sr = r;
         z = r * ((-c.kl * h) * Math<R>::rcp(xc));
     }
 }
@@ -242,9 +246,9 @@ __device__ __forceinline__ void o_coeffs(const Consts<R>& c, R x, R h, R& su, R&
 // o_coeffs and the drift coefficients of a step of length h at X, a h and b h (one square
 // root of H - X_c serves both; a, b as in drift_at).
 template <typename R, int PROF>
-__device__ __forceinline__ void coeffs_at(const Consts<R>& c, R x, R h, R& su, R& z, R& ah, R& bh) {
+__device__ __forceinline__ void coeffs_at(const Consts<R>& c, R x, R h, R& sr, R& z, R& ah, R& bh) {
     if (PROF == KPROFILE_HOMOGENEOUS) {
-        su = c.su_h;
+        sr = (R)1;
         z = -c.lam_h * h;
         ah = (R)0;
         bh = (R)0;
@@ -254,7 +258,7 @@ __device__ __forceinline__ void coeffs_at(const Consts<R>& c, R x, R h, R& su, R
         R sqd, invd;
         Math<R>::sqrt_and_rcp(d, sqd, invd);
         const R r = Math<R>::sqrt_(d * sqd);
-        su = c.ksH * r;
+        sr = r;
         z = r * ((-c.kl * h) * Math<R>::rcp(xc));
         // inside [eps_reg, H - eps_reg] exactly when the cut-off leaves X as it is
         const bool inside = xc == x;
@@ -268,7 +272,8 @@ __device__ __forceinline__ void coeffs_at(const Consts<R>& c, R x, R h, R& su, R
 // [eps_reg, H - eps_reg], 0 outside. The half-step is then U - a hh - (b hh) U^2.
 // ONE_CMP: the inside test as one vector compare against the cut-off position (no scalar
 // combination of two compares waits on the path's chain); otherwise two compares. Both
-// give the same answer.
+// give the same answer. FP32 takes q = 1/sqrt(H - X), set to 0 outside, once:
+// a hh = (a' hh (H - X)) q and b hh = (b' hh q) q, so one select serves both.
 template <typename R, int PROF, bool ONE_CMP = false>
 __device__ __forceinline__ void drift_at(const Consts<R>& c, R x, R hh, R& ah, R& bh) {
     if (PROF == KPROFILE_HOMOGENEOUS) {
@@ -276,10 +281,17 @@ __device__ __forceinline__ void drift_at(const Consts<R>& c, R x, R hh, R& ah, R
         bh = (R)0;
     } else {
         const bool inside = ONE_CMP ? Math<R>::clamp_(x, c.eps, c.Hme) == x : (x >= c.eps) && (x <= c.Hme);
-        R sq, inv;
-        Math<R>::sqrt_and_rcp(c.H - x, sq, inv);
-        ah = inside ? (c.acoef_h * hh) * sq : (R)0;
-        bh = inside ? ((R)0.75 * hh) * inv : (R)0;
+        const R d = c.H - x;
+        if constexpr (sizeof(R) == 4) {
+            const R q = inside ? Math<R>::rsqrt(d) : (R)0;
+            ah = ((c.acoef_h * hh) * d) * q;
+            bh = (((R)0.75 * hh) * q) * q;
+        } else {
+            R sq, inv;
+            Math<R>::sqrt_and_rcp(d, sq, inv);
+            ah = inside ? (c.acoef_h * hh) * sq : (R)0;
+            bh = inside ? ((R)0.75 * hh) * inv : (R)0;
+        }
     }
 }
 
@@ -378,18 +390,20 @@ __device__ __forceinline__ int expm1_tier(const KProblem& kp, int integ, double 
     return z <= (double)Math<R>::kTinyZ ? 2 : (z <= (double)Math<R>::kSmallZ ? 1 : 0);
 }
 
-// One step of size h. COARSE: xi is the combined extended noise and the physical noise
-// is S xi; otherwise xi is the physical noise and `tilde` receives S xi. `w` receives
-// e^{-lambda h} of the O-step (GL, BAOAB). TIER: see o_step_expm1.
+// One step of size h. The normals a step takes are scaled by sxi (sigma_U = sxi sr), so
+// sigma_U xi is sr times the scaled normal. COARSE: xi is the combined extended noise
+// (scaled) and the physical noise is S xi; otherwise xi is the physical noise (scaled)
+// and `tilde` receives S xi. `w` receives e^{-lambda h} of the O-step (GL, BAOAB).
+// TIER: see o_step_expm1.
 template <typename R, int INTEG, int PROF, bool COARSE, int TIER, int FOLD>
 __device__ __forceinline__ void step_impl(const Consts<R>& c, Path<R>& p, R h, R hh, R xi,
                                           R& tilde, R& w, uint32_t& key) {
     if (INTEG == KINTEG_SE) {                                        // Eq. (8)
-        R su, z, ah, bh;                                             // z = -lambda h
-        coeffs_at<R, PROF>(c, p.x, h, su, z, ah, bh);
+        R sr, z, ah, bh;                                             // z = -lambda h
+        coeffs_at<R, PROF>(c, p.x, h, sr, z, ah, bh);
         const R noise = COARSE ? Math<R>::flip(xi, p.sgn) : xi;
         if (!COARSE) tilde = Math<R>::flip(xi, p.sgn);
-        const R amp = su * Math<R>::sqrt_((R)-2 * z);                  // sigma sqrt(h)
+        const R amp = sr * Math<R>::sqrt_((R)-2 * z);                  // sigma sqrt(h) / sxi
         const R u0 = p.u;
         const R lin = ((R)1 + z) * u0 - ah;                          // (1 - lambda h) U - a h
         p.u = Math<R>::fma_(amp, noise, lin - (bh * u0) * u0);       // - b h U^2 + sigma dW
@@ -397,13 +411,13 @@ __device__ __forceinline__ void step_impl(const Consts<R>& c, Path<R>& p, R h, R
         fold_or_track<R, FOLD>(p, c.H, key);
         w = (R)1;
     } else if (INTEG == KINTEG_GL) {                                 // Eq. (9)
-        R su, z, ah, bh;
-        coeffs_at<R, PROF>(c, p.x, h, su, z, ah, bh);
+        R sr, z, ah, bh;
+        coeffs_at<R, PROF>(c, p.x, h, sr, z, ah, bh);
         const R noise = COARSE ? Math<R>::flip(xi, p.sgn) : xi;
         if (!COARSE) tilde = Math<R>::flip(xi, p.sgn);
         const R e1 = o_step_expm1<R, TIER>(z);
         w = (R)1 + e1;
-        const R sn = su * noise;
+        const R sn = sr * noise;                                     // sigma_U xi
         const R us = Math<R>::fma_(sn, Math<R>::sqrt_(-e1 * ((R)2 + e1)), w * p.u);   // O
         p.u = kick(us, ah, bh);                                      // B at (X_n, U*)
         p.x = p.x + p.u * h;                                         // A
@@ -412,13 +426,13 @@ __device__ __forceinline__ void step_impl(const Consts<R>& c, Path<R>& p, R h, R
         p.u = kick(p.u, p.a, p.b);                                   // B at (X_n, U_n)
         p.x = p.x + p.u * hh;                                        // A
         fold_or_track<R, FOLD>(p, c.H, key);
-        R su, z;
-        o_coeffs<R, PROF>(c, p.x, h, su, z);
+        R sr, z;
+        o_coeffs<R, PROF>(c, p.x, h, sr, z);
         const R noise = COARSE ? Math<R>::flip(xi, p.sgn) : xi;
         if (!COARSE) tilde = Math<R>::flip(xi, p.sgn);
         const R e1 = o_step_expm1<R, TIER>(z);
         w = (R)1 + e1;
-        const R sn = su * noise;
+        const R sn = sr * noise;                                     // sigma_U xi
         p.u = Math<R>::fma_(sn, Math<R>::sqrt_(-e1 * ((R)2 + e1)), w * p.u);   // O at X_{n+1/2}
         p.x = p.x + p.u * hh;                                        // A
         fold_or_track<R, FOLD>(p, c.H, key);
@@ -471,6 +485,14 @@ __device__ __forceinline__ void init_path(const Consts<R>& c, Path<R>& p, R x0, 
     if (INTEG == KINTEG_BAOAB) drift_at<R, PROF>(c, x0, hh, p.a, p.b);
 }
 
+// The two normals of draw m, scaled by sxi as the steps take them.
+template <typename R>
+__device__ __forceinline__ void scaled_normals(const Consts<R>& c, const Words& wd, R& z0, R& z1) {
+    Normals<R>::pair(wd, z0, z1);
+    z0 *= c.sxi;
+    z1 *= c.sxi;
+}
+
 // The time loop of one sample: M_l fine steps and, on levels >= 1, M_l / 2 coarse
 // steps driven by the combined fine noise. TIER_F and TIER_C: o_step_expm1's tier for
 // the fine path (step h) and the coarse path (step 2h).
@@ -480,18 +502,18 @@ __device__ __forceinline__ void run_paths(const Consts<R>& c, const Stream& st, 
     R tilde_a, tilde_b, w_a, w_b, z0, z1;
     if (level == 0) {
         for (uint32_t m = 0; m < M / 2; ++m) {
-            Normals<R>::pair(philox(st, m), z0, z1);
+            scaled_normals(c, philox(st, m), z0, z1);
             step<R, INTEG, PROF, false, TIER_F>(c, f, h, hh, z0, tilde_a, w_a);
             step<R, INTEG, PROF, false, TIER_F>(c, f, h, hh, z1, tilde_b, w_b);
         }
         if (M & 1u) {
-            Normals<R>::pair(philox(st, M / 2), z0, z1);
+            scaled_normals(c, philox(st, M / 2), z0, z1);
             step<R, INTEG, PROF, false, TIER_F>(c, f, h, hh, z0, tilde_a, w_a);
         }
         return;
     }
     for (uint32_t m = 0; m < M / 2; ++m) {
-        Normals<R>::pair(philox(st, m), z0, z1);
+        scaled_normals(c, philox(st, m), z0, z1);
         step<R, INTEG, PROF, false, TIER_F>(c, f, h, hh, z0, tilde_a, w_a);   // fine step 2m
         step<R, INTEG, PROF, false, TIER_F>(c, f, h, hh, z1, tilde_b, w_b);   // fine step 2m+1
         R xi_c;

@@ -172,53 +172,59 @@ __device__ __forceinline__ void accumulate(Acc& acc, double pf, double pc, bool 
 }
 
 // PIPE mode (coupled levels only): 64 samples per block. Waves 0 and 1 draw the
-// normals of alternate coarse steps of a chunk, wave 2 advances the fine paths over
-// the chunk before and passes (S xi_2m, S xi_2m+1, e^{-lambda h}) on, wave 3 advances
-// the coarse paths over the chunk before that. Double-buffered LDS, one barrier per
-// chunk of kPipeChunk coarse steps; the arithmetic per path is that of STREAM mode.
+// (scaled) normals of alternate coarse steps of a chunk, wave 2 advances the fine paths
+// over the chunk before and wave 3 the coarse paths over the chunk before that. The
+// coarse wave forms S xi itself from the normals and the fine path's S over the chunk,
+// which the fine wave publishes once per chunk with e^{-lambda h} of every first step of
+// a pair. Normals are triple-buffered (drawn, fine, coarse), messages double-buffered;
+// one barrier per chunk of kPipeChunk coarse steps; the arithmetic per path is that of
+// STREAM mode.
 template <typename R>
 struct PipeLds {
-    R nrm[2][kPipeChunk][2][64];   // normals of a chunk, double-buffered
-    R msg[2][kPipeChunk][3][64];   // fine -> coarse: S xi_2m, S xi_2m+1, e^{-lambda h}
+    R nrm[3][kPipeChunk][2][64];   // scaled normals of a chunk (S xi after a repeated chunk)
+    R msg[2][kPipeChunk][64];      // fine -> coarse: e^{-lambda h} of fine step 2m
+    uint32_t sgn[2][64];           // fine -> coarse: the fine path's S over the chunk
     double end_pc[64];
     int end_bad[64];
 };
 
 // Fine wave of a wave-specialised block: K fine step pairs of one chunk (fine steps
-// 2m, 2m + 1 for m = m0 .. m0 + K - 1 below P), reading the normals of buffer b and
-// publishing S xi of both steps and w of the first for the coarse wave. The chunk runs
-// first without folds, tracking how far its positions went (FOLD_TRACK): a path stays
-// in [0, H] on almost every chunk, and then no position test or branch sits on the
-// chain of its steps. A lane whose positions left [0, H] repeats the chunk from its
-// saved state with folded steps and publishes again, so every lane ends with the
-// folded steps' results bit for bit.
-template <typename R, int INTEG, int PROF, int TIER>
+// 2m, 2m + 1 for m = m0 .. m0 + K - 1 below P), reading the normals of buffer b3. The
+// chunk runs first without folds, tracking how far its positions went (FOLD_TRACK): a
+// path stays in [0, H] on almost every chunk, and then no position test or branch sits
+// on the chain of its steps and S is the same for the whole chunk. A lane whose
+// positions left [0, H] repeats the chunk from its saved state with folded steps,
+// writes each step's S xi over its normal and publishes S = +1, so every lane ends with
+// the folded steps' results bit for bit and the coarse wave reads the right S xi
+// either way. FULL: all K step pairs lie below P (every chunk but a ragged last one),
+// so the tracked pass has no per-pair test and is one straight run.
+template <typename R, int INTEG, int PROF, int TIER, bool FULL>
 __device__ __forceinline__ void pipe_fine_chunk(const Consts<R>& c, Path<R>& p, R h, R hh,
-                                                PipeLds<R>& L, uint32_t b, uint32_t m0,
-                                                uint32_t P, int lane) {
+                                                PipeLds<R>& L, uint32_t b3, uint32_t b2,
+                                                uint32_t m0, uint32_t P, int lane) {
     const Path<R> p0 = p;
     uint32_t key = 0;
     for (int j = 0; j < kPipeChunk; ++j) {
-        if (m0 + j < P) {
+        if (FULL || m0 + j < P) {
             R ta, tb, wa, wb;
-            step_impl<R, INTEG, PROF, false, TIER, FOLD_TRACK>(c, p, h, hh, L.nrm[b][j][0][lane], ta, wa, key);
-            step_impl<R, INTEG, PROF, false, TIER, FOLD_TRACK>(c, p, h, hh, L.nrm[b][j][1][lane], tb, wb, key);
-            L.msg[b][j][0][lane] = ta;
-            L.msg[b][j][1][lane] = tb;
-            L.msg[b][j][2][lane] = wa;
+            step_impl<R, INTEG, PROF, false, TIER, FOLD_TRACK>(c, p, h, hh, L.nrm[b3][j][0][lane], ta, wa, key);
+            step_impl<R, INTEG, PROF, false, TIER, FOLD_TRACK>(c, p, h, hh, L.nrm[b3][j][1][lane], tb, wb, key);
+            if (INTEG != KINTEG_SE) L.msg[b2][j][lane] = wa;
         }
     }
-    if (__builtin_expect(key > FoldKey<R>::limit(c.H), 0)) {
+    const bool repeat = key > FoldKey<R>::limit(c.H);
+    L.sgn[b2][lane] = repeat ? 0u : p0.sgn;
+    if (__builtin_expect(repeat, 0)) {
         p = p0;
 #pragma unroll 1
         for (int j = 0; j < kPipeChunk; ++j) {
             if (m0 + j < P) {
                 R ta, tb, wa, wb;
-                step<R, INTEG, PROF, false, TIER>(c, p, h, hh, L.nrm[b][j][0][lane], ta, wa);
-                step<R, INTEG, PROF, false, TIER>(c, p, h, hh, L.nrm[b][j][1][lane], tb, wb);
-                L.msg[b][j][0][lane] = ta;
-                L.msg[b][j][1][lane] = tb;
-                L.msg[b][j][2][lane] = wa;
+                step<R, INTEG, PROF, false, TIER>(c, p, h, hh, L.nrm[b3][j][0][lane], ta, wa);
+                step<R, INTEG, PROF, false, TIER>(c, p, h, hh, L.nrm[b3][j][1][lane], tb, wb);
+                L.nrm[b3][j][0][lane] = ta;
+                L.nrm[b3][j][1][lane] = tb;
+                if (INTEG != KINTEG_SE) L.msg[b2][j][lane] = wa;
             }
         }
     }
@@ -229,16 +235,18 @@ __device__ __forceinline__ void pipe_fine_chunk(const Consts<R>& c, Path<R>& p, 
 // without folds first and a lane whose positions left [0, H] repeats it with them.
 template <typename R, int INTEG, int PROF, int FOLD, int TIER>
 __device__ __forceinline__ void coarse_steps(const Consts<R>& c, Path<R>& p, R h2, R h,
-                                             PipeLds<R>& L, uint32_t b, uint32_t m0,
-                                             uint32_t P, int lane, uint32_t& key) {
+                                             PipeLds<R>& L, uint32_t b3, uint32_t b2,
+                                             uint32_t m0, uint32_t P, int lane, uint32_t& key) {
+    const uint32_t sf = L.sgn[b2][lane];
     for (int j = 0; j < kPipeChunk; ++j) {
         if (m0 + j < P) {
-            const R ta = L.msg[b][j][0][lane], tb = L.msg[b][j][1][lane];
+            const R ta = Math<R>::flip(L.nrm[b3][j][0][lane], sf);
+            const R tb = Math<R>::flip(L.nrm[b3][j][1][lane], sf);
             R xi_c;
             if (INTEG == KINTEG_SE) {
                 xi_c = (ta + tb) * (R)0.70710678118654752440;             // Eq. (18)
             } else {
-                const R wa = L.msg[b][j][2][lane];
+                const R wa = L.msg[b2][j][lane];
                 xi_c = (wa * ta + tb) * Math<R>::rsqrt(wa * wa + (R)1);  // Eq. (19)
             }
             R unused_t, unused_w;
@@ -249,14 +257,14 @@ __device__ __forceinline__ void coarse_steps(const Consts<R>& c, Path<R>& p, R h
 
 template <typename R, int INTEG, int PROF, int TIER>
 __device__ __forceinline__ void pipe_coarse_chunk(const Consts<R>& c, Path<R>& p, R h2, R h,
-                                                  PipeLds<R>& L, uint32_t b, uint32_t m0,
-                                                  uint32_t P, int lane) {
+                                                  PipeLds<R>& L, uint32_t b3, uint32_t b2,
+                                                  uint32_t m0, uint32_t P, int lane) {
     const Path<R> p0 = p;
     uint32_t key = 0;
-    coarse_steps<R, INTEG, PROF, FOLD_TRACK, TIER>(c, p, h2, h, L, b, m0, P, lane, key);
+    coarse_steps<R, INTEG, PROF, FOLD_TRACK, TIER>(c, p, h2, h, L, b3, b2, m0, P, lane, key);
     if (__builtin_expect(key > FoldKey<R>::limit(c.H), 0)) {
         p = p0;
-        coarse_steps<R, INTEG, PROF, FOLD_EXACT, TIER>(c, p, h2, h, L, b, m0, P, lane, key);
+        coarse_steps<R, INTEG, PROF, FOLD_EXACT, TIER>(c, p, h2, h, L, b3, b2, m0, P, lane, key);
     }
 }
 
@@ -287,42 +295,53 @@ __device__ __forceinline__ void pipe_samples(const KProblem& kp, const Consts<R>
         initial_state<R, PROF>(kp, c, st, x0, u0);
         init_path<R, INTEG, PROF>(c, p, x0, u0, wave == 2 ? hh : h);   // fine or coarse B half-step
     }
+    // phase s: the normal waves fill chunk s (buffer s mod 3), the fine wave runs chunk
+    // s - 1 and the coarse wave chunk s - 2
+    uint32_t r3 = 0;   // s mod 3
     for (uint32_t s = 0; s < nch + 2; ++s) {
         if (wave < 2) {
             if (s < nch) {
-                const uint32_t b = s & 1;
 #pragma unroll
                 for (int j = 0; j < K; j += 2) {
                     const uint32_t m = s * K + j + wave;
                     if (m < P) {
                         R z0, z1;
-                        Normals<R>::pair(philox(st, m), z0, z1);
-                        nrm[b][j + wave][0][lane] = z0;
-                        nrm[b][j + wave][1][lane] = z1;
+                        scaled_normals(c, philox(st, m), z0, z1);
+                        nrm[r3][j + wave][0][lane] = z0;
+                        nrm[r3][j + wave][1][lane] = z1;
                     }
                 }
             }
         } else if (wave == 2) {
             if (s >= 1 && s <= nch) {
-                const uint32_t b = (s - 1) & 1;
-                if (tier_f == 2)
-                    pipe_fine_chunk<R, INTEG, PROF, 2>(c, p, h, hh, L, b, (s - 1) * K, P, lane);
-                else if (tier_f == 1)
-                    pipe_fine_chunk<R, INTEG, PROF, 1>(c, p, h, hh, L, b, (s - 1) * K, P, lane);
-                else
-                    pipe_fine_chunk<R, INTEG, PROF, 0>(c, p, h, hh, L, b, (s - 1) * K, P, lane);
+                const uint32_t b3 = r3 == 0 ? 2u : r3 - 1, b2 = (s - 1) & 1, m0 = (s - 1) * K;
+                if (m0 + K <= P) {
+                    if (tier_f == 2)
+                        pipe_fine_chunk<R, INTEG, PROF, 2, true>(c, p, h, hh, L, b3, b2, m0, P, lane);
+                    else if (tier_f == 1)
+                        pipe_fine_chunk<R, INTEG, PROF, 1, true>(c, p, h, hh, L, b3, b2, m0, P, lane);
+                    else
+                        pipe_fine_chunk<R, INTEG, PROF, 0, true>(c, p, h, hh, L, b3, b2, m0, P, lane);
+                } else if (tier_f == 2) {
+                    pipe_fine_chunk<R, INTEG, PROF, 2, false>(c, p, h, hh, L, b3, b2, m0, P, lane);
+                } else if (tier_f == 1) {
+                    pipe_fine_chunk<R, INTEG, PROF, 1, false>(c, p, h, hh, L, b3, b2, m0, P, lane);
+                } else {
+                    pipe_fine_chunk<R, INTEG, PROF, 0, false>(c, p, h, hh, L, b3, b2, m0, P, lane);
+                }
             }
         } else {
             if (s >= 2) {
-                const uint32_t b = s & 1;   // == (s - 2) & 1
+                const uint32_t b3 = r3 == 2 ? 0u : r3 + 1, b2 = s & 1, m0 = (s - 2) * K;   // (s - 2) mod 3, mod 2
                 if (tier_c == 2)
-                    pipe_coarse_chunk<R, INTEG, PROF, 2>(c, p, h2, h, L, b, (s - 2) * K, P, lane);
+                    pipe_coarse_chunk<R, INTEG, PROF, 2>(c, p, h2, h, L, b3, b2, m0, P, lane);
                 else if (tier_c == 1)
-                    pipe_coarse_chunk<R, INTEG, PROF, 1>(c, p, h2, h, L, b, (s - 2) * K, P, lane);
+                    pipe_coarse_chunk<R, INTEG, PROF, 1>(c, p, h2, h, L, b3, b2, m0, P, lane);
                 else
-                    pipe_coarse_chunk<R, INTEG, PROF, 0>(c, p, h2, h, L, b, (s - 2) * K, P, lane);
+                    pipe_coarse_chunk<R, INTEG, PROF, 0>(c, p, h2, h, L, b3, b2, m0, P, lane);
             }
         }
+        r3 = r3 == 2 ? 0u : r3 + 1;
         __syncthreads();
     }
     if (wave == 3) {
