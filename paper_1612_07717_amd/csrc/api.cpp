@@ -45,7 +45,7 @@ double lambda_at(const ld_profile& prof, double x) {
 int validate_problem(const ld_problem* p) {
     if (p == nullptr) return fail(LD_EINVAL, "problem is NULL");
     const ld_profile& f = p->profile;
-    if (!(finite(f.H) && f.H > 0)) return fail(LD_EINVAL, "profile.H must be positive");
+    if (!(finite(f.H) && f.H >= 1e-6 && f.H <= 1e30)) return fail(LD_EINVAL, "profile.H must be in [1e-6, 1e30]");
     if (f.kind == LD_PROFILE_HOMOGENEOUS) {
         if (!(finite(f.sigma_u) && f.sigma_u > 0 && finite(f.tau) && f.tau > 0))
             return fail(LD_EINVAL, "homogeneous profile needs sigma_u > 0 and tau > 0");

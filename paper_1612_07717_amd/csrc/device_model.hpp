@@ -310,35 +310,6 @@ struct Path {
     bool bad;       // ran away (more than kFoldMax reflections): non-finite
 };
 
-// Fold into [0, H]; 0 and H are inside. More than kFoldMax reflections in one fold
-// means the step ran away: the path becomes NaN and is counted as non-finite.
-template <typename R>
-__device__ __forceinline__ void fold(Path<R>& p, R H) {
-    if (__builtin_expect(Math<R>::outside(p.x, H), 0)) {
-        int count = 0;
-#pragma unroll 1
-        do {
-            if (++count > kFoldMax) {
-                p.x = (R)NAN;
-                p.u = (R)NAN;
-                p.bad = true;
-                break;
-            }
-            p.x = (p.x < (R)0) ? -p.x : (R)2 * H - p.x;
-            p.u = -p.u;
-            p.sgn ^= kSignBit;
-        } while (p.x < (R)0 || p.x > H);
-    }
-}
-
-
-// How a step treats its position updates. FOLD_EXACT folds each one (fold()).
-// FOLD_TRACK leaves them unfolded and only records, in `key`, the largest fold key
-// (FoldKey) of the positions reached: for positions in [0, H] fold() changes nothing,
-// so while every key stays within FoldKey::limit(H) the tracked steps are the exact
-// steps bit for bit, and otherwise the caller repeats them with FOLD_EXACT.
-enum { FOLD_EXACT = 0, FOLD_TRACK = 1 };
-
 // A position's fold key: an unsigned number that exceeds limit(H) for every position
 // outside [0, H], for -0 and for NaN. FP32: the bit pattern itself (non-negative
 // floats order as their patterns; a sign bit makes the pattern larger than any positive
@@ -358,6 +329,36 @@ struct FoldKey<double> {
     static __device__ __forceinline__ uint32_t key(double x) { return (uint32_t)__double2hiint(x); }
     static __device__ __forceinline__ uint32_t limit(double H) { return (uint32_t)__double2hiint(H) - 1u; }
 };
+
+// Fold into [0, H]; 0 and H are inside. More than kFoldMax reflections in one fold
+// means the step ran away: the path becomes NaN and is counted as non-finite. The
+// branch is entered on one unsigned compare of the fold key (which also lets -0, NaN and,
+// in FP64, the last 2^-20 of H below it through); the loop's own test is the exact one.
+template <typename R>
+__device__ __forceinline__ void fold(Path<R>& p, R H) {
+    if (__builtin_expect(FoldKey<R>::key(p.x) > FoldKey<R>::limit(H), 0)) {
+        int count = 0;
+#pragma unroll 1
+        while (Math<R>::outside(p.x, H)) {
+            if (++count > kFoldMax) {
+                p.x = (R)NAN;
+                p.u = (R)NAN;
+                p.bad = true;
+                break;
+            }
+            p.x = (p.x < (R)0) ? -p.x : (R)2 * H - p.x;
+            p.u = -p.u;
+            p.sgn ^= kSignBit;
+        }
+    }
+}
+
+// How a step treats its position updates. FOLD_EXACT folds each one (fold()).
+// FOLD_TRACK leaves them unfolded and only records, in `key`, the largest fold key
+// (FoldKey) of the positions reached: for positions in [0, H] fold() changes nothing,
+// so while every key stays within FoldKey::limit(H) the tracked steps are the exact
+// steps bit for bit, and otherwise the caller repeats them with FOLD_EXACT.
+enum { FOLD_EXACT = 0, FOLD_TRACK = 1 };
 
 template <typename R, int FOLD>
 __device__ __forceinline__ void fold_or_track(Path<R>& p, R H, uint32_t& key) {
