@@ -24,6 +24,15 @@ HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
                "-fno-fast-math", "-ffp-contract=on", "-Wall", "-Wno-unused-function"]
 
 
+# The same library with AddressSanitizer and UndefinedBehaviorSanitizer in its host code
+# (every flag goes behind -Xarch_host; the device code is the product's). A GPU test runs
+# a C client against it that drives the driver, the engine, the server and the p.d.f.
+# estimator.
+HOSTSAN_LIB = os.path.join(HERE, "libldmlmc_hostsan.so")
+HOSTSAN_FLAGS = ["-fsanitize=address", "-fsanitize=undefined", "-fno-sanitize-recover=all",
+                 "-fno-omit-frame-pointer", "-g"]
+
+
 def hipcc() -> str:
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc"):
         if cand and os.path.exists(cand):
@@ -47,6 +56,19 @@ def build(verbose: bool = False, out: str = LIB, host_flags=()) -> str:
         print("\n".join(msgs), file=sys.stderr)
     os.replace(tmp, out)
     return out
+
+
+def build_hostsan(verbose: bool = False) -> str:
+    return build(verbose=verbose, out=HOSTSAN_LIB, host_flags=HOSTSAN_FLAGS)
+
+
+def hostsan_is_current() -> bool:
+    """True if the sanitizer build exists and is newer than every source and header."""
+    if not os.path.exists(HOSTSAN_LIB):
+        return False
+    inputs = [os.path.join(CSRC, f) for f in os.listdir(CSRC)] + \
+             [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include"))]
+    return os.path.getmtime(HOSTSAN_LIB) >= max(os.path.getmtime(f) for f in inputs)
 
 
 if __name__ == "__main__":

@@ -59,7 +59,9 @@ def test_library_host_code_under_sanitizers(tmp_path):
     rts = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
     if not rts:
         pytest.skip("clang's AddressSanitizer runtime is not installed")
-    lib = libbuild.build(out=str(tmp_path / "libldmlmc_san.so"), host_flags=FLAGS)
+    # the in-tree sanitizer build if it is current, else a fresh one
+    lib = libbuild.HOSTSAN_LIB if libbuild.hostsan_is_current() else \
+        libbuild.build(out=str(tmp_path / "libldmlmc_san.so"), host_flags=libbuild.HOSTSAN_FLAGS)
     env = dict(os.environ, LDMLMC_LIB=lib, LD_PRELOAD=rts[-1],
                ASAN_OPTIONS="detect_leaks=0:alloc_dealloc_mismatch=0",
                UBSAN_OPTIONS="print_stacktrace=1")
