@@ -454,7 +454,8 @@ def adaptive_report(ld, precisions=("fp64", "fp32"), n_bias=1 << 22):
 
 def batched_report(ld, steps, warmup, autotune=True):
     """64 independent estimators (mixed release height, tolerance, integrator and QoI)
-    in one live engine: autotuned FP32 (or the default options), the same options in
+    in one live engine (ld_engine_run, which submits, steps and collects in the library):
+    autotuned FP32 (or the default options), the same options in
     FP64 (also the one-call form that creates its engine), and the same queries one at a
     time through mlmc_estimate in FP64 with a preallocated workspace. Each precision's
     roofline counts the algorithmic operations of every query's coupled steps over the
@@ -467,37 +468,18 @@ def batched_report(ld, steps, warmup, autotune=True):
         best, t_tune = ld.autotune(queries, reps=3, precision="fp32")   # median of 3 per configuration
     else:
         best, t_tune = ld.engine_opts(precision="fp32"), 0.0
-    def run_all(engine):
-        """All queries to completion on a live engine (submitted as slots free up)."""
-        handles, out, nxt = [None] * len(queries), [None] * len(queries), 0
-        while any(r is None for r in out):
-            while nxt < len(queries):
-                h = engine.submit(queries[nxt])
-                if h is None:
-                    break
-                handles[nxt] = h
-                nxt += 1
-            engine.step()
-            for i in range(nxt):
-                if out[i] is None:
-                    r = engine.result(handles[i])
-                    if r is not None:
-                        out[i] = r
-                        engine.release(handles[i])
-        return out
-
     res = {}
     for prec in ("fp32", "fp64"):
         o = ld.engine_opts(**dict(ld.opts_dict(best), precision=prec))
         # a live engine, as a server keeps it: its allocation is not timed
         with ld.Engine(o) as eng:
             for _ in range(warmup):
-                run_all(eng)
+                eng.run(queries)
             torch.cuda.synchronize()
             dev0 = eng.stats()["device_seconds"]
             t0 = time.perf_counter()
             for _ in range(steps):
-                out = run_all(eng)
+                out = eng.run(queries)
             dt = (time.perf_counter() - t0) / steps
             dev_s = (eng.stats()["device_seconds"] - dev0) / steps
         # the one-call form, which creates and frees an engine (about 1 GiB) each time

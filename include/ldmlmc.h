@@ -442,6 +442,13 @@ int ld_engine_release(ld_engine* engine, int64_t handle);
 int ld_engine_stats(ld_engine* engine, double* device_seconds, int64_t* iterations,
                     double* fine_steps);
 
+/* Runs n queries to completion on a live engine: submits them in order as slots free
+   up, steps until every one has finished, fills out[0..n-1] and releases their handles;
+   queries already admitted by the caller run along (their results stay for
+   ld_engine_result). The queries are validated first (LD_EINVAL / LD_EUNSTABLE, nothing
+   submitted). Returns the worst status of the n queries (an error, else a warning, else
+   LD_OK); after an error the engine may still hold some of them. */
+int ld_engine_run(ld_engine* engine, const ld_query* queries, int32_t n, ld_estimate_result* out);
 /* Runs n queries to completion on one engine (submitting as slots free up) and fills
    out[0..n-1]. Returns the worst status. */
 int mlmc_estimate_batch(const ld_query* queries, int32_t n, const ld_engine_opts* opts,

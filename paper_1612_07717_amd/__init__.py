@@ -32,6 +32,7 @@ EXPORTED = ["mlmc_level_sums_workspace", "mlmc_level_sums", "mlmc_level_sums_noa
             "mlmc_estimate_default_opts", "mlmc_estimate_workspace", "mlmc_estimate",
             "ld_engine_default_opts", "ld_engine_create", "ld_engine_destroy", "ld_engine_submit",
             "ld_engine_step", "ld_engine_result", "ld_engine_release", "ld_engine_stats",
+            "ld_engine_run",
             "mlmc_pdf_level_sums_workspace", "mlmc_pdf_level_sums", "mlmc_plan_pdf",
             "mlmc_estimate_pdf", "mlmc_estimate_pdf_workspace",
             "mlmc_estimate_batch", "ld_engine_autotune",
@@ -236,6 +237,7 @@ def load():
     lib.ld_engine_release.argtypes = [C.c_void_p, C.c_int64]
     lib.ld_engine_stats.argtypes = [C.c_void_p, P(C.c_double), P(C.c_int64), P(C.c_double)]
     lib.mlmc_estimate_batch.argtypes = [P(Query), C.c_int32, P(EngineOpts), P(EstimateResult)]
+    lib.ld_engine_run.argtypes = [C.c_void_p, P(Query), C.c_int32, P(EstimateResult)]
     lib.ld_engine_autotune.argtypes = [P(Query), C.c_int32, P(EngineOpts), C.c_int32,
                                        P(EngineOpts), P(C.c_double)]
     lib.mlmc_pdf_level_sums_workspace.argtypes = [C.c_uint64, C.c_int32]
@@ -573,6 +575,15 @@ class Engine:
 
     def release(self, handle: int):
         _check(self._lib.ld_engine_release(self._h, int(handle)))
+
+    def run(self, queries: list) -> list:
+        """ld_engine_run: the queries to completion on this engine (submitted as slots free
+        up), their result dicts in order."""
+        arr = (Query * len(queries))(*queries)
+        res = (EstimateResult * len(queries))()
+        rc = self._lib.ld_engine_run(self._h, arr, len(queries), res)
+        _check(rc, ok=(LD_OK, LD_WARN_NOT_CONVERGED, LD_ENONFINITE))
+        return [_result_dict(r, r.status) for r in res]
 
     def stats(self) -> dict:
         d, it, fs = C.c_double(), C.c_int64(), C.c_double()

@@ -74,11 +74,13 @@ struct ld_engine {
     ld_level_sums* d_range_out = nullptr;
     KTile* d_tiles = nullptr;
     ld_level_sums* d_partials = nullptr;
-    KHeader* h_hdr = nullptr;
-    KRange* h_ranges = nullptr;
+    KHeader* h_hdr = nullptr;              // pinned: the header, then the ranges at rng_off,
+    KRange* h_ranges = nullptr;            // laid out as d_hdr and d_ranges (one upload)
+    size_t rng_off = 0;
     KProblem* h_problems = nullptr;        // pinned copy of every slot's problem
     int32_t new_lo = 0, new_hi = -1;       // slots whose problems await upload
-    ld_level_sums* h_running = nullptr;
+    ld_level_sums* h_running = nullptr;    // pinned, coherent: the range merge writes it
+    ld_level_sums* h_running_dev = nullptr;   // its address on the device
     hipGraphExec_t graph[1 << kNumQueues] = {};   // by queue mask
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     std::vector<Query> q;        // by slot
@@ -120,7 +122,6 @@ void release_resources(ld_engine* e) {
     if (e->ev1) (void)hipEventDestroy(e->ev1);
     if (e->d_base) (void)hipFree(e->d_base);
     if (e->h_hdr) (void)hipHostFree(e->h_hdr);
-    if (e->h_ranges) (void)hipHostFree(e->h_ranges);
     if (e->h_problems) (void)hipHostFree(e->h_problems);
     if (e->h_running) (void)hipHostFree(e->h_running);
     if (e->own_stream && e->stream) (void)hipStreamDestroy(e->stream);
@@ -166,7 +167,7 @@ int capture_graph(ld_engine* e, uint32_t mask) {
     const uint32_t grids[kNumQueues] = {e->grid, e->grid, e->grid};
     int rc = launch_engine_iteration(e->opts.precision, true, grids, mask, e->d_hdr, e->d_tiles, e->d_problems,
                                      e->d_partials, e->d_counters, e->d_ranges, e->d_running,
-                                     e->d_range_out, e->stream);
+                                     e->d_range_out, e->h_running_dev, e->stream);
     const hipError_t ec = hipStreamEndCapture(e->stream, &g);
     if (rc != LD_OK || ec != hipSuccess) {
         if (g) (void)hipGraphDestroy(g);
@@ -245,11 +246,12 @@ int ld_engine_create(const ld_engine_opts* opts_in, ld_engine** out) {
     e->max_tiles = (o.hbm_budget_bytes - fixed - slots * per_slot) / per_tile;
     e->max_tiles = std::min<uint64_t>(e->max_tiles, (uint64_t)1 << 31);
     size_t off = 0;
+    // the header and the range table back to back, as in the pinned staging: one upload
     const size_t o_hdr = off; off = align_up(off + sizeof(KHeader), 256);
+    const size_t o_rng = off; off = align_up(off + e->max_ranges * sizeof(KRange), 256);
     const size_t o_cnt = off; off = align_up(off + 64, 256);
     const size_t o_prob = off; off = align_up(off + slots * sizeof(KProblem), 256);
     const size_t o_run = off; off = align_up(off + slots * LD_MAX_LEVELS * sizeof(ld_level_sums), 256);
-    const size_t o_rng = off; off = align_up(off + e->max_ranges * sizeof(KRange), 256);
     const size_t o_rout = off; off = align_up(off + e->max_ranges * sizeof(ld_level_sums), 256);
     const size_t o_tile = off; off = align_up(off + e->max_tiles * sizeof(KTile), 256);
     const size_t o_part = off; off = align_up(off + e->max_tiles * sizeof(ld_level_sums), 256);
@@ -266,15 +268,19 @@ int ld_engine_create(const ld_engine_opts* opts_in, ld_engine** out) {
     e->d_range_out = (ld_level_sums*)(b + o_rout);
     e->d_tiles = (KTile*)(b + o_tile);
     e->d_partials = (ld_level_sums*)(b + o_part);
-    if (hipHostMalloc((void**)&e->h_hdr, sizeof(KHeader)) != hipSuccess ||
-        hipHostMalloc((void**)&e->h_ranges, e->max_ranges * sizeof(KRange)) != hipSuccess ||
-        hipHostMalloc((void**)&e->h_running, slots * LD_MAX_LEVELS * sizeof(ld_level_sums)) != hipSuccess ||
+    e->rng_off = o_rng - o_hdr;
+    if (hipHostMalloc((void**)&e->h_hdr, e->rng_off + e->max_ranges * sizeof(KRange)) != hipSuccess ||
+        hipHostMalloc((void**)&e->h_running, slots * LD_MAX_LEVELS * sizeof(ld_level_sums),
+                      hipHostMallocCoherent | hipHostMallocMapped) != hipSuccess ||
+        hipHostGetDevicePointer((void**)&e->h_running_dev, e->h_running, 0) != hipSuccess ||
         hipHostMalloc((void**)&e->h_problems, slots * sizeof(KProblem)) != hipSuccess) {
         release_resources(e);
         delete e;
         return fail(LD_ENOMEM, "pinned host staging allocation failed");
     }
+    e->h_ranges = (KRange*)((char*)e->h_hdr + e->rng_off);
     std::memset(e->h_problems, 0, slots * sizeof(KProblem));
+    std::memset(e->h_running, 0, slots * LD_MAX_LEVELS * sizeof(ld_level_sums));
     if (o.hip_stream != nullptr) {
         e->stream = (hipStream_t)o.hip_stream;
     } else {
@@ -434,9 +440,8 @@ int ld_engine_step(ld_engine* e, int32_t* n_active) {
         return fail(LD_EDEVICE, "uploading the new problems failed");
     e->new_lo = 0;
     e->new_hi = -1;
-    if (hipMemcpyAsync(e->d_hdr, e->h_hdr, sizeof(KHeader), hipMemcpyHostToDevice, e->stream) != hipSuccess ||
-        hipMemcpyAsync(e->d_ranges, e->h_ranges, nr * sizeof(KRange), hipMemcpyHostToDevice, e->stream) !=
-            hipSuccess)
+    if (hipMemcpyAsync(e->d_hdr, e->h_hdr, e->rng_off + nr * sizeof(KRange), hipMemcpyHostToDevice,
+                       e->stream) != hipSuccess)
         return fail(LD_EDEVICE, "uploading the tile tables failed");
     if (e->opts.use_graph && e->graph[mask] == nullptr) {
         rc = capture_graph(e, mask);
@@ -452,19 +457,13 @@ int ld_engine_step(ld_engine* e, int32_t* n_active) {
         for (int qi = 0; qi < kNumQueues; ++qi) grids[qi] = (uint32_t)std::max<uint64_t>(1, count[qi]);
         rc = launch_engine_iteration(e->opts.precision, false, grids, mask, e->d_hdr, e->d_tiles, e->d_problems,
                                          e->d_partials, e->d_counters, e->d_ranges, e->d_running,
-                                         e->d_range_out, e->stream);
+                                         e->d_range_out, e->h_running_dev, e->stream);
         if (rc != LD_OK) return fail(rc, "engine launch failed");
     }
     (void)hipEventRecord(e->ev1, e->stream);
-    int32_t smin = e->slots, smax = -1;
-    for (const Pending& p : pall) {
-        smin = std::min(smin, p.slot);
-        smax = std::max(smax, p.slot);
-    }
+    // the range merge wrote every updated row into h_running as well
     const size_t row = LD_MAX_LEVELS * sizeof(ld_level_sums);
-    if (hipMemcpyAsync((char*)e->h_running + smin * row, (char*)e->d_running + smin * row,
-                       (size_t)(smax - smin + 1) * row, hipMemcpyDeviceToHost, e->stream) != hipSuccess ||
-        hipStreamSynchronize(e->stream) != hipSuccess)
+    if (hipStreamSynchronize(e->stream) != hipSuccess)
         return fail(LD_EDEVICE, std::string("engine iteration failed: ") + hipGetErrorString(hipGetLastError()));
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, e->ev0, e->ev1) == hipSuccess) e->device_seconds += 1e-3 * ms;
@@ -606,6 +605,16 @@ static int run_to_completion(ld_engine* e, const ld_query* queries, int32_t n, l
         }
     }
     return worst;
+}
+
+int ld_engine_run(ld_engine* e, const ld_query* queries, int32_t n, ld_estimate_result* out) {
+    if (e == nullptr) return fail(LD_EINVAL, "engine is NULL");
+    if (queries == nullptr || out == nullptr || n < 1) return fail(LD_EINVAL, "need n >= 1 queries");
+    for (int32_t i = 0; i < n; ++i) {
+        const int rc = validate_query(&queries[i]);
+        if (rc != LD_OK) return rc;
+    }
+    return run_to_completion(e, queries, n, out);
 }
 
 int mlmc_estimate_batch(const ld_query* queries, int32_t n, const ld_engine_opts* opts,

@@ -706,7 +706,8 @@ __global__ __launch_bounds__(kBlock) void merge_ranges_kernel(const KHeader* __r
                                                               const ld_level_sums* __restrict__ partials,
                                                               ld_level_sums* __restrict__ running,
                                                               ld_level_sums* __restrict__ range_out,
-                                                              uint32_t* __restrict__ counters) {
+                                                              uint32_t* __restrict__ counters,
+                                                              ld_level_sums* __restrict__ host_running) {
     if (blockIdx.x == 0 && threadIdx.x < (unsigned)kNumQueues) counters[threadIdx.x] = 0u;
     const uint32_t n_ranges = hdr->n_ranges;
     for (uint32_t r = blockIdx.x; r < n_ranges; r += gridDim.x) {
@@ -742,6 +743,10 @@ __global__ __launch_bounds__(kBlock) void merge_ranges_kernel(const KHeader* __r
             tot.n += acc.n;
             tot.nbad += acc.nbad;
             store_sums(run, tot);
+            // the same row into the host's pinned copy (one lane: a posted write over the
+            // bus), which the host reads after the stream synchronises
+            if (host_running != nullptr && (threadIdx.x & 63) == 0)
+                store_sums(&host_running[rg.slot * LD_MAX_LEVELS + rg.level], tot);
         }
     }
 }
@@ -955,7 +960,7 @@ int launch_engine_iteration(int precision, bool persistent, const uint32_t* grid
                             const KHeader* d_hdr, const KTile* d_tiles, const KProblem* d_problems,
                             ld_level_sums* d_partials, uint32_t* d_counters,
                             const KRange* d_ranges, ld_level_sums* d_running,
-                            ld_level_sums* d_range_out, void* stream) {
+                            ld_level_sums* d_range_out, ld_level_sums* h_running, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     hipLaunchKernelGGL(expand_tiles_kernel, dim3(kMergeGrid), dim3(kBlock), 0, s, d_hdr, d_ranges,
                        (KTile*)d_tiles);
@@ -966,7 +971,7 @@ int launch_engine_iteration(int precision, bool persistent, const uint32_t* grid
         launch_queues<double>(persistent, grid_blocks, queue_mask, s, d_hdr, d_tiles, d_problems, d_partials,
                               d_counters);
     hipLaunchKernelGGL(merge_ranges_kernel, dim3(kMergeGrid), dim3(kBlock), 0, s, d_hdr, d_ranges, d_partials,
-                       d_running, d_range_out, d_counters);
+                       d_running, d_range_out, d_counters, h_running);
     return hipGetLastError() == hipSuccess ? LD_OK : LD_EDEVICE;
 }
 

@@ -144,7 +144,7 @@ int launch_engine_iteration(int precision, bool persistent, const uint32_t* grid
                             const KHeader* d_hdr, const KTile* d_tiles, const KProblem* d_problems,
                             ld_level_sums* d_partials, uint32_t* d_counters,
                             const KRange* d_ranges, ld_level_sums* d_running,
-                            ld_level_sums* d_range_out, void* stream);
+                            ld_level_sums* d_range_out, ld_level_sums* h_running, void* stream);
 // Binned concentration: bins [a0 + i width, a0 + (i+1) width], i < n_bins (<= 64),
 // over a dump of n (X_f, X_c) pairs of `level`.
 struct KBins {

@@ -49,6 +49,20 @@ def test_batch_equals_single_estimates():
     assert not all(rel for _, _, rel in cfgs) and any(rel for _, _, rel in cfgs)
 
 
+def test_engine_run_equals_batch_and_keeps_the_engine():
+    """ld_engine_run on a live engine gives mlmc_estimate_batch's results bit for bit, twice
+    in a row on the same engine (each query's sums start from zero when it is admitted)."""
+    cfgs = _mixed_configs(9, seed=17)
+    qs = [_query(c, e, rel, N_init=1000, L_max=9) for c, e, rel in cfgs]
+    ref = ld.estimate_batch(qs, precision="fp32", max_queries=4)
+    with ld.Engine(precision="fp32", max_queries=4) as eng:   # fewer slots than queries
+        for rep in range(2):
+            got = eng.run(qs)
+            for r, g in zip(ref, got):
+                assert g["N"] == r["N"] and g["estimate"] == r["estimate"], rep
+        assert eng.stats()["iterations"] > 0
+
+
 def test_alone_equals_mixed_bitwise():
     cfgs = _mixed_configs(12, seed=5)
     q0 = _query(*cfgs[0], N_init=2000, L_max=10)

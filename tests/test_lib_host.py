@@ -176,6 +176,7 @@ def test_batch_validates_queries_before_device_use(lib):
     arr = (ld.Query * 1)(unstable)
     assert lib.mlmc_estimate_batch(arr, 1, None, res) == ld.LD_EUNSTABLE
     assert lib.mlmc_estimate_batch(arr, 0, None, res) == ld.LD_EINVAL
+    assert lib.ld_engine_run(None, arr, 1, res) == ld.LD_EINVAL
 
 
 def test_server_rejects_bad_arguments_without_device(lib):
