@@ -99,12 +99,22 @@ void merge_into(HostSums& acc, const ld_level_sums& add) {
 // of sqrt(V_k C_k) over the short levels only, each N_l is at most what the full rule will
 // ask once the long levels are known (for an absolute eps; for a relative one the short
 // levels' partial estimate stands in, and the long levels' corrections are small). That
-// many (kEarlyFraction of it) are drawn at once, on the second stream, while the long
-// levels still run; the ordinary iterations follow, usually with little left to draw. The draws are the same (sample indices from 0 upward on every
-// level), only their order in time changes, so the estimate is the plain MLMC estimate
-// of whatever N_l end up drawn.
+// many are drawn at once, on the second stream, while the long levels still run; the
+// ordinary iterations follow. The sum of sqrt(V_k C_k) in that rule also counts the long
+// levels, whose variances are not known yet, by extending the short levels' terms
+// geometrically: term_k = term_Ls rho^(k - Ls), with rho the ratio of the last two short
+// terms clamped to [kRhoMin, 1] (a variance that decays like 2^-beta l with beta between
+// 1 and 3), times kLongMargin; and each short level's count is raised by three standard
+// errors of its variance estimate, 3 sqrt(2 / n_l), so that the full rule, applied with
+// the variances of all samples, rarely asks for more than its 1 % tolerance. Where the
+// guess is high the short levels get a few more samples than the full rule asks, which
+// run beside the long levels anyway; where it is low the first ordinary iteration draws
+// the rest, as without the guess. The draws are
+// the same (sample indices from 0 upward on every level), only their order in time
+// changes, so the estimate is the plain MLMC estimate of whatever N_l end up drawn.
 constexpr int32_t kEarlyGap = 5;
-constexpr double kEarlyFraction = 1.0;
+constexpr double kRhoMin = 0.5;
+constexpr double kLongMargin = 1.25;
 
 // The second stream and the events of an estimate, kept for reuse instead of being made
 // and destroyed by every call. A kit belongs to one device and to one call at a time:
@@ -412,11 +422,25 @@ int mlmc_estimate(double eps, const ld_qoi* qoi, ld_integrator integrator, const
                 ld_plan_out po;
                 mlmc_plan(&ps, &po);
                 uint64_t dn_s[LD_MAX_LEVELS] = {0};
+                // the variance rule with the long levels' terms extrapolated (see above)
+                double term[LD_MAX_LEVELS], s_short = 0.0;
                 for (int32_t l = 0; l <= Ls; ++l) {
-                    const double want = std::floor(kEarlyFraction * ((double)ps.n[l] + (double)po.dn[l]));
-                    dn_s[l] = (want > (double)ps.n[l]) ? (uint64_t)want - ps.n[l] : 0;
+                    term[l] = std::sqrt(std::max(po.V[l], 0.0) * std::ldexp((double)opts.M0, l));
+                    s_short += term[l];
                 }
-                if (po.status == 0 && !exceeds_budget(opts.max_fine_steps, opts.M0, drawn, dn_s, Ls))
+                const double rho = (Ls >= 1 && term[Ls - 1] > 0.0)
+                                       ? std::min(1.0, std::max(kRhoMin, term[Ls] / term[Ls - 1])) : 1.0;
+                double s_long = 0.0, t = term[Ls];
+                for (int32_t k = Ls + 1; k <= L0; ++k) s_long += (t *= rho);
+                const double scale = 2.0 * (s_short + kLongMargin * s_long) / (po.eps_abs * po.eps_abs);
+                for (int32_t l = 0; l <= Ls; ++l) {
+                    const double margin = 1.0 + 3.0 * std::sqrt(2.0 / (double)std::max<uint64_t>(ps.n[l], 2));
+                    const double want = std::ceil(margin * scale * std::sqrt(std::max(po.V[l], 0.0) /
+                                                                             std::ldexp((double)opts.M0, l)));
+                    dn_s[l] = (std::isfinite(want) && want > (double)ps.n[l])
+                                  ? (uint64_t)std::min(want, 1e15) - ps.n[l] : 0;
+                }
+                if (po.eps_abs > 0.0 && !exceeds_budget(opts.max_fine_steps, opts.M0, drawn, dn_s, Ls))
                     for (int32_t l = 0; l <= Ls; ++l) topb.add(l, drawn[l], dn_s[l]);
                 if (topb.n > 0) {
                     (void)hipEventRecord(e_short0, s2);

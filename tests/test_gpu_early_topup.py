@@ -7,7 +7,9 @@ schedule (indices from 0 on every level), so:
   [0, N_l) on every level, recomputed on the CPU) within 1e-11;
 - the run is deterministic (two calls agree bit for bit);
 - it converges like the plain schedule, to an estimate within the statistical error, and
-  draws at least 0.9 of the plain schedule's samples on the short levels;
+  draws between 0.9 and 1.25 times the plain schedule's samples on the short levels (the
+  long levels' share of the variance rule is extrapolated, and each count carries a
+  margin of three standard errors of its variance estimate: 1.095 at N_init = 2000);
 - too few levels (L0 < 5) and fixed_N fall back to the plain schedule exactly.
 """
 import sys
@@ -53,7 +55,7 @@ def test_deterministic_and_consistent_with_the_plain_schedule():
     assert a["rmse_est"] <= 1e-3 * abs(a["estimate"]) * 1.01
     assert abs(a["estimate"] - p["estimate"]) <= 3.0 * np.sqrt(a["stat_var"] + p["stat_var"])
     for l in range(3):                      # short levels 0..L0-5
-        assert a["N"][l] >= 0.9 * p["N"][l] - 1
+        assert 0.9 * p["N"][l] - 1 <= a["N"][l] <= 1.25 * p["N"][l] + 1
 
 
 def test_falls_back_to_the_plain_schedule():
