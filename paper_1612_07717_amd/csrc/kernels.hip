@@ -657,9 +657,10 @@ __global__ __launch_bounds__(kBlock) void persistent_kernel(const KHeader* __res
 }
 
 // One block per tile (a grid of exactly the queue's tile count): blocks start in tile
-// order, so the longest paths, first in the table, start first.
+// order, so the longest paths, first in the table, start first. At least three waves per
+// SIMD, as for the level kernels (the FP64 body then fits 168 VGPRs without spilling).
 template <typename R, int PROF, bool ADAPT = false>
-__global__ __launch_bounds__(kBlock) void tile_kernel(const KHeader* __restrict__ hdr,
+__global__ __launch_bounds__(kBlock, 3) void tile_kernel(const KHeader* __restrict__ hdr,
                                                       const KTile* __restrict__ tiles,
                                                       const KProblem* __restrict__ problems,
                                                       ld_level_sums* __restrict__ partials) {
