@@ -432,17 +432,30 @@ int ld_engine_step(ld_engine* e, int32_t* n_active) {
         first += count[qi];
     }
     e->h_hdr->n_ranges = nr;
-    // 3. upload (new problems, header, ranges: one copy each), run, read back
-    if (e->new_hi >= 0 &&
-        hipMemcpyAsync(&e->d_problems[e->new_lo], &e->h_problems[e->new_lo],
-                       (size_t)(e->new_hi - e->new_lo + 1) * sizeof(KProblem), hipMemcpyHostToDevice,
-                       e->stream) != hipSuccess)
-        return fail(LD_EDEVICE, "uploading the new problems failed");
+    // 3. the tables of a small iteration go as the expand kernel's argument (no copy
+    //    queued); larger ones, and captured graphs, upload new problems, then header and
+    //    ranges, one copy each
+    const int32_t n_new = e->new_hi >= 0 ? e->new_hi - e->new_lo + 1 : 0;
+    const bool small = !e->opts.use_graph && nr <= (uint32_t)kInlineRanges && n_new <= kInlineProblems;
+    KInline inl;
+    if (small) {
+        std::memset(&inl, 0, sizeof inl);
+        inl.hdr = *e->h_hdr;
+        inl.new_lo = (uint32_t)(n_new > 0 ? e->new_lo : 0);
+        inl.n_new = (uint32_t)n_new;
+        std::memcpy(inl.ranges, e->h_ranges, nr * sizeof(KRange));
+        if (n_new > 0) std::memcpy(inl.problems, &e->h_problems[e->new_lo], (size_t)n_new * sizeof(KProblem));
+    } else {
+        if (n_new > 0 &&
+            hipMemcpyAsync(&e->d_problems[e->new_lo], &e->h_problems[e->new_lo], (size_t)n_new * sizeof(KProblem),
+                           hipMemcpyHostToDevice, e->stream) != hipSuccess)
+            return fail(LD_EDEVICE, "uploading the new problems failed");
+        if (hipMemcpyAsync(e->d_hdr, e->h_hdr, e->rng_off + nr * sizeof(KRange), hipMemcpyHostToDevice,
+                           e->stream) != hipSuccess)
+            return fail(LD_EDEVICE, "uploading the tile tables failed");
+    }
     e->new_lo = 0;
     e->new_hi = -1;
-    if (hipMemcpyAsync(e->d_hdr, e->h_hdr, e->rng_off + nr * sizeof(KRange), hipMemcpyHostToDevice,
-                       e->stream) != hipSuccess)
-        return fail(LD_EDEVICE, "uploading the tile tables failed");
     if (e->opts.use_graph && e->graph[mask] == nullptr) {
         rc = capture_graph(e, mask);
         if (rc != LD_OK) return rc;
@@ -457,7 +470,7 @@ int ld_engine_step(ld_engine* e, int32_t* n_active) {
         for (int qi = 0; qi < kNumQueues; ++qi) grids[qi] = (uint32_t)std::max<uint64_t>(1, count[qi]);
         rc = launch_engine_iteration(e->opts.precision, false, grids, mask, e->d_hdr, e->d_tiles, e->d_problems,
                                          e->d_partials, e->d_counters, e->d_ranges, e->d_running,
-                                         e->d_range_out, e->h_running_dev, e->stream);
+                                         e->d_range_out, e->h_running_dev, e->stream, small ? &inl : nullptr);
         if (rc != LD_OK) return fail(rc, "engine launch failed");
     }
     (void)hipEventRecord(e->ev1, e->stream);

@@ -694,6 +694,37 @@ __global__ __launch_bounds__(kBlock) void expand_tiles_kernel(const KHeader* __r
     }
 }
 
+// expand_tiles_kernel for a small iteration whose tables come as the argument: block 0
+// stores the header, the ranges and the new problems for the kernels that follow (stream
+// order), and every block writes its ranges' tiles from the argument.
+__global__ __launch_bounds__(kBlock) void expand_inline_kernel(const KInline in, KHeader* __restrict__ hdr,
+                                                               KRange* __restrict__ ranges,
+                                                               KProblem* __restrict__ problems,
+                                                               KTile* __restrict__ tiles) {
+    const uint32_t n_ranges = in.hdr.n_ranges;
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) *hdr = in.hdr;
+        for (uint32_t r = threadIdx.x; r < n_ranges; r += kBlock) ranges[r] = in.ranges[r];
+        for (uint32_t j = threadIdx.x; j < in.n_new; j += kBlock) problems[in.new_lo + j] = in.problems[j];
+    }
+    for (uint32_t r = blockIdx.x; r < n_ranges; r += gridDim.x) {
+        const KRange& rg = in.ranges[r];
+        KTile t;
+        t.slot = rg.slot;
+        t.level = rg.level;
+        t.sample_begin = rg.sample_begin;
+        t.n_samples = rg.n_samples;
+        t.spl = rg.spl;
+        t.mode = rg.mode;
+        t.prio = rg.prio;
+        t.pad = 0;
+        for (uint32_t b = threadIdx.x; b < rg.n_tiles; b += kBlock) {
+            t.local_block = b;
+            tiles[rg.tile_begin + b] = t;
+        }
+    }
+}
+
 __global__ void reset_counters_kernel(uint32_t* counters, int n) {
     if ((int)threadIdx.x < n) counters[threadIdx.x] = 0u;
 }
@@ -961,10 +992,16 @@ int launch_engine_iteration(int precision, bool persistent, const uint32_t* grid
                             const KHeader* d_hdr, const KTile* d_tiles, const KProblem* d_problems,
                             ld_level_sums* d_partials, uint32_t* d_counters,
                             const KRange* d_ranges, ld_level_sums* d_running,
-                            ld_level_sums* d_range_out, ld_level_sums* h_running, void* stream) {
+                            ld_level_sums* d_range_out, ld_level_sums* h_running, void* stream,
+                            const KInline* inl) {
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(expand_tiles_kernel, dim3(kMergeGrid), dim3(kBlock), 0, s, d_hdr, d_ranges,
-                       (KTile*)d_tiles);
+    if (inl != nullptr)
+        hipLaunchKernelGGL(expand_inline_kernel, dim3(inl->hdr.n_ranges > 0 ? inl->hdr.n_ranges : 1u), dim3(kBlock),
+                           0, s, *inl, const_cast<KHeader*>(d_hdr), const_cast<KRange*>(d_ranges),
+                           const_cast<KProblem*>(d_problems), const_cast<KTile*>(d_tiles));
+    else
+        hipLaunchKernelGGL(expand_tiles_kernel, dim3(kMergeGrid), dim3(kBlock), 0, s, d_hdr, d_ranges,
+                           (KTile*)d_tiles);
     if (precision == LD_FP32)
         launch_queues<float>(persistent, grid_blocks, queue_mask, s, d_hdr, d_tiles, d_problems, d_partials,
                              d_counters);

@@ -133,18 +133,33 @@ struct KRange {
 
 constexpr int kMergeGrid = 256;   // blocks of the range-merge kernel (grid-stride)
 
+// A small iteration's tables as one kernel argument (under 4 KB): the header, the ranges
+// and the problems of newly admitted queries (slots new_lo .. new_lo + n_new - 1). The
+// expand kernel stores them where the larger iterations' uploads go, so no copy is queued.
+constexpr int kInlineRanges = 24;
+constexpr int kInlineProblems = 4;
+struct KInline {
+    KHeader hdr;
+    uint32_t new_lo, n_new, pad[2];
+    KRange ranges[kInlineRanges];
+    KProblem problems[kInlineProblems];
+};
+static_assert(sizeof(KInline) <= 3584, "an inline iteration must fit the kernel argument space");
+
 // Enqueues one engine iteration: the tile table written from the ranges, then for each
 // queue whose bit (1 << KPROFILE_*,
 // 1 << KQUEUE_ADAPT) is set in queue_mask, its tiles in grid_blocks[queue] blocks, either
 // persistent ones that take tiles from the queue's counter (a fixed grid, for captured
 // graphs) or one block per tile (grid_blocks[queue] = its tile count); then the range
 // merge into the running sums, which also sets the queue counters back to zero (they
-// must be zero when an iteration starts).
+// must be zero when an iteration starts). inl (not NULL): the tables come as the expand
+// kernel's argument and it stores the header, ranges and new problems first.
 int launch_engine_iteration(int precision, bool persistent, const uint32_t* grid_blocks, uint32_t queue_mask,
                             const KHeader* d_hdr, const KTile* d_tiles, const KProblem* d_problems,
                             ld_level_sums* d_partials, uint32_t* d_counters,
                             const KRange* d_ranges, ld_level_sums* d_running,
-                            ld_level_sums* d_range_out, ld_level_sums* h_running, void* stream);
+                            ld_level_sums* d_range_out, ld_level_sums* h_running, void* stream,
+                            const KInline* inl = nullptr);
 // Binned concentration: bins [a0 + i width, a0 + (i+1) width], i < n_bins (<= 64),
 // over a dump of n (X_f, X_c) pairs of `level`.
 struct KBins {
