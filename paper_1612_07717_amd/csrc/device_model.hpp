@@ -272,8 +272,9 @@ __device__ __forceinline__ void coeffs_at(const Consts<R>& c, R x, R h, R& sr, R
 // [eps_reg, H - eps_reg], 0 outside. The half-step is then U - a hh - (b hh) U^2.
 // ONE_CMP: the inside test as one vector compare against the cut-off position (no scalar
 // combination of two compares waits on the path's chain); otherwise two compares. Both
-// give the same answer. FP32 takes q = 1/sqrt(H - X), set to 0 outside, once:
-// a hh = (a' hh (H - X)) q and b hh = (b' hh q) q, so one select serves both.
+// give the same answer. Both precisions take q = 1/sqrt(H - X), set to 0 outside, once:
+// a hh = (a' hh (H - X)) q and b hh = (b' hh q) q, so one reciprocal square root and one
+// select serve both coefficients.
 template <typename R, int PROF, bool ONE_CMP = false>
 __device__ __forceinline__ void drift_at(const Consts<R>& c, R x, R hh, R& ah, R& bh) {
     if (PROF == KPROFILE_HOMOGENEOUS) {
@@ -282,16 +283,9 @@ __device__ __forceinline__ void drift_at(const Consts<R>& c, R x, R hh, R& ah, R
     } else {
         const bool inside = ONE_CMP ? Math<R>::clamp_(x, c.eps, c.Hme) == x : (x >= c.eps) && (x <= c.Hme);
         const R d = c.H - x;
-        if constexpr (sizeof(R) == 4) {
-            const R q = inside ? Math<R>::rsqrt(d) : (R)0;
-            ah = ((c.acoef_h * hh) * d) * q;
-            bh = (((R)0.75 * hh) * q) * q;
-        } else {
-            R sq, inv;
-            Math<R>::sqrt_and_rcp(d, sq, inv);
-            ah = inside ? (c.acoef_h * hh) * sq : (R)0;
-            bh = inside ? ((R)0.75 * hh) * inv : (R)0;
-        }
+        const R q = inside ? Math<R>::rsqrt(d) : (R)0;
+        ah = ((c.acoef_h * hh) * d) * q;
+        bh = (((R)0.75 * hh) * q) * q;
     }
 }
 
