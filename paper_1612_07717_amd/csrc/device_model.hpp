@@ -255,15 +255,15 @@ __device__ __forceinline__ void coeffs_at(const Consts<R>& c, R x, R h, R& sr, R
     } else {
         const R xc = Math<R>::clamp_(x, c.eps, c.Hme);
         const R d = c.H - xc;
-        R sqd, invd;
-        Math<R>::sqrt_and_rcp(d, sqd, invd);
-        const R r = Math<R>::sqrt_(d * sqd);
+        const R q = Math<R>::rsqrt(d);                       // 1/sqrt(H - X_c)
+        const R r = Math<R>::sqrt_(d * (d * q));
         sr = r;
         z = r * ((-c.kl * h) * Math<R>::rcp(xc));
-        // inside [eps_reg, H - eps_reg] exactly when the cut-off leaves X as it is
-        const bool inside = xc == x;
-        ah = inside ? (c.acoef_h * h) * sqd : (R)0;
-        bh = inside ? ((R)0.75 * h) * invd : (R)0;
+        // inside [eps_reg, H - eps_reg] exactly when the cut-off leaves X as it is; there
+        // X_c = X, and one select of q serves both drift coefficients (as in drift_at)
+        const R qm = (xc == x) ? q : (R)0;
+        ah = ((c.acoef_h * h) * d) * qm;
+        bh = (((R)0.75 * h) * qm) * qm;
     }
 }
 
