@@ -535,8 +535,8 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=5.0,
                     help="single_large: seconds of the short serving run (0 = none)")
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--integrator", default="BAOAB", choices=["BAOAB", "GL"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
