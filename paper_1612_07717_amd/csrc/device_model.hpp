@@ -267,25 +267,26 @@ __device__ __forceinline__ void coeffs_at(const Consts<R>& c, R x, R h, R& sr, R
     }
 }
 
-// The drift coefficients of a B half-step of length hh at X: a hh and b hh, with
+// The drift coefficients of a B half-step of length hh at X, with
 // a = (3/4)(kappa_sigma u_*)^2 sqrt(H - X) / H^(3/2) and b = (3/4) / (H - X) inside
-// [eps_reg, H - eps_reg], 0 outside. The half-step is then U - a hh - (b hh) U^2.
-// ONE_CMP: the inside test as one vector compare against the cut-off position (no scalar
-// combination of two compares waits on the path's chain); otherwise two compares. Both
-// give the same answer. Both precisions take q = 1/sqrt(H - X), set to 0 outside, once:
-// a hh = (a' hh (H - X)) q and b hh = (b' hh q) q, so one reciprocal square root and one
-// select serve both coefficients.
+// [eps_reg, H - eps_reg], 0 outside: ah = a hh and sb = sqrt(b hh), so that the half-step
+// is U - ah - (sb U)^2 (kick_sb). ONE_CMP: the inside test as one vector compare against
+// the cut-off position (no scalar combination of two compares waits on the path's
+// chain); otherwise two compares. Both give the same answer. q = 1/sqrt(H - X), set to 0
+// outside, is taken once: ah = (a' hh (H - X)) q and sb = sqrt(3 hh / 4) q, one
+// reciprocal square root and one select for both (sqrt(3 hh / 4) is the same for every
+// step of a path).
 template <typename R, int PROF, bool ONE_CMP = false>
-__device__ __forceinline__ void drift_at(const Consts<R>& c, R x, R hh, R& ah, R& bh) {
+__device__ __forceinline__ void drift_at(const Consts<R>& c, R x, R hh, R& ah, R& sb) {
     if (PROF == KPROFILE_HOMOGENEOUS) {
         ah = (R)0;
-        bh = (R)0;
+        sb = (R)0;
     } else {
         const bool inside = ONE_CMP ? Math<R>::clamp_(x, c.eps, c.Hme) == x : (x >= c.eps) && (x <= c.Hme);
         const R d = c.H - x;
         const R q = inside ? Math<R>::rsqrt(d) : (R)0;
         ah = ((c.acoef_h * hh) * d) * q;
-        bh = (((R)0.75 * hh) * q) * q;
+        sb = Math<R>::sqrt_((R)0.75 * hh) * q;
     }
 }
 
@@ -296,11 +297,19 @@ __device__ __forceinline__ R kick(R u, R ah, R bh) {
     return (u - ah) - (bh * u) * u;
 }
 
+// The same half-step with b' given by its square root sb (drift_at): U - a' - (sb U)^2.
+// Two BAOAB half-steps share one (ah, sb), so b' itself is never formed.
+template <typename R>
+__device__ __forceinline__ R kick_sb(R u, R ah, R sb) {
+    const R t = sb * u;
+    return (u - ah) - t * t;
+}
+
 template <typename R>
 struct Path {
     R x, u;
     uint32_t sgn;   // reflection sign S as a sign-bit mask (0: S = +1)
-    R a, b;         // BAOAB: a hh and b hh of drift_at at x, carried to the next step
+    R a, b;         // BAOAB: ah and sb of drift_at at x, carried to the next step
     bool bad;       // ran away (more than kFoldMax reflections): non-finite
 };
 
@@ -418,7 +427,7 @@ __device__ __forceinline__ void step_impl(const Consts<R>& c, Path<R>& p, R h, R
         p.x = p.x + p.u * h;                                         // A
         fold_or_track<R, FOLD>(p, c.H, key);
     } else {                                                         // Eq. (10)
-        p.u = kick(p.u, p.a, p.b);                                   // B at (X_n, U_n)
+        p.u = kick_sb(p.u, p.a, p.b);                                // B at (X_n, U_n)
         p.x = p.x + p.u * hh;                                        // A
         fold_or_track<R, FOLD>(p, c.H, key);
         R sr, z;
@@ -432,7 +441,7 @@ __device__ __forceinline__ void step_impl(const Consts<R>& c, Path<R>& p, R h, R
         p.x = p.x + p.u * hh;                                        // A
         fold_or_track<R, FOLD>(p, c.H, key);
         drift_at<R, PROF, FOLD == FOLD_TRACK>(c, p.x, hh, p.a, p.b);
-        p.u = kick(p.u, p.a, p.b);                                   // B at (X_{n+1}, U*)
+        p.u = kick_sb(p.u, p.a, p.b);                                // B at (X_{n+1}, U*)
     }
 }
 
