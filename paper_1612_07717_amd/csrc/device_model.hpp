@@ -422,7 +422,9 @@ __device__ __forceinline__ void step_impl(const Consts<R>& c, Path<R>& p, R h, R
         const R e1 = o_step_expm1<R, TIER>(z);
         w = (R)1 + e1;
         const R sn = sr * noise;                                     // sigma_U xi
-        const R us = Math<R>::fma_(sn, Math<R>::sqrt_(-e1 * ((R)2 + e1)), w * p.u);   // O
+        // O: e^{-lambda h} U = U + e1 U in one fused multiply-add (w itself only for the
+        // coupling of Eq. 19)
+        const R us = Math<R>::fma_(sn, Math<R>::sqrt_(-e1 * ((R)2 + e1)), Math<R>::fma_(e1, p.u, p.u));
         p.u = kick(us, ah, bh);                                      // B at (X_n, U*)
         p.x = p.x + p.u * h;                                         // A
         fold_or_track<R, FOLD>(p, c.H, key);
@@ -437,6 +439,8 @@ __device__ __forceinline__ void step_impl(const Consts<R>& c, Path<R>& p, R h, R
         const R e1 = o_step_expm1<R, TIER>(z);
         w = (R)1 + e1;
         const R sn = sr * noise;                                     // sigma_U xi
+        // (w U here: U + e1 U, as in GL, saves half an operation per step but measured 2 %
+        // slower on the BAOAB fine wave's schedule)
         p.u = Math<R>::fma_(sn, Math<R>::sqrt_(-e1 * ((R)2 + e1)), w * p.u);   // O at X_{n+1/2}
         p.x = p.x + p.u * hh;                                        // A
         fold_or_track<R, FOLD>(p, c.H, key);
