@@ -81,7 +81,8 @@ enum {
    tau = kappa_tau X / sigma_U (Eq. 5), frozen below eps_reg and above H - eps_reg
    (Eq. 7). HOMOGENEOUS: constant sigma_u and tau. Valid: 1e-6 <= H <= 1e30 (a height
    in metres; the bounds keep H a normal number in both path precisions); NEUTRAL_BL needs
-   kappa_sigma, kappa_tau, u_star > 0 and 0 < eps_reg < H/2; HOMOGENEOUS needs
+   kappa_sigma, kappa_tau, u_star > 0 and 1e-6 H <= eps_reg < H/2 (a band the FP32 path
+   arithmetic resolves); HOMOGENEOUS needs
    sigma_u > 0 and tau > 0. */
 typedef struct {
     int32_t kind;

@@ -53,8 +53,11 @@ int validate_problem(const ld_problem* p) {
         if (!(finite(f.kappa_sigma) && f.kappa_sigma > 0 && finite(f.kappa_tau) &&
               f.kappa_tau > 0 && finite(f.u_star) && f.u_star > 0))
             return fail(LD_EINVAL, "neutral profile needs kappa_sigma, kappa_tau, u_star > 0");
-        if (!(finite(f.eps_reg) && f.eps_reg > 0 && f.eps_reg < 0.5 * f.H))
-            return fail(LD_EINVAL, "neutral profile needs 0 < eps_reg < H/2");
+        // the cut-off band must be resolved by the FP32 path arithmetic: with eps_reg
+        // below H's rounding, H - eps_reg would round to H and the drift coefficients at
+        // X = H, which would count as inside, would divide by zero
+        if (!(finite(f.eps_reg) && f.eps_reg >= 1e-6 * f.H && f.eps_reg < 0.5 * f.H))
+            return fail(LD_EINVAL, "neutral profile needs 1e-6 H <= eps_reg < H/2");
     } else {
         return fail(LD_EINVAL, "unknown profile kind");
     }

@@ -125,7 +125,7 @@ def _call_level_sums(lib, cfg, level=0, n=100, ws_bytes=None, integ=None):
 def test_validation_rejects_bad_problems_without_device(lib):
     good = W.neutral(300.0, "GL")
     bad = [dict(good, H=-1.0), dict(W.homogeneous(), H=1e-300, z0=0.0), dict(W.homogeneous(), H=1e31),
-           dict(good, eps_reg=600.0), dict(good, eps_reg=0.0),
+           dict(good, eps_reg=600.0), dict(good, eps_reg=0.0), dict(good, eps_reg=1e-4),
            dict(good, kappa_tau=0.0), dict(good, z0=1200.0), dict(good, T=0.0),
            dict(good, M0=0), dict(good, stream_id=1 << 24),
            dict(good, qoi="p_box", r=9, delta=100.0), dict(good, qoi="p_box", r=4, delta=0.0),
