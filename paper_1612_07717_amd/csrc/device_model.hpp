@@ -269,47 +269,37 @@ __device__ __forceinline__ void coeffs_at(const Consts<R>& c, R x, R h, R& sr, R
 
 // The drift coefficients of a B half-step of length hh at X, with
 // a = (3/4)(kappa_sigma u_*)^2 sqrt(H - X) / H^(3/2) and b = (3/4) / (H - X) inside
-// [eps_reg, H - eps_reg], 0 outside: ah = a hh and sb = sqrt(b hh), so that the half-step
-// is U - ah - (sb U)^2 (kick_sb). ONE_CMP: the inside test as one vector compare against
-// the cut-off position (no scalar combination of two compares waits on the path's
-// chain); otherwise two compares. Both give the same answer. q = 1/sqrt(H - X), set to 0
-// outside, is taken once: ah = (a' hh (H - X)) q and sb = sqrt(3 hh / 4) q, one
-// reciprocal square root and one select for both (sqrt(3 hh / 4) is the same for every
-// step of a path).
+// [eps_reg, H - eps_reg], 0 outside: ah = a hh and bh = b hh (kick). ONE_CMP: the inside
+// test as one vector compare against the cut-off position (no scalar combination of two
+// compares waits on the path's chain); otherwise two compares. Both give the same
+// answer. q = 1/sqrt(H - X), set to 0 outside, is taken once: ah = (a' hh (H - X)) q and
+// bh = ((3 hh / 4) q) q, one reciprocal square root and one select for both.
 template <typename R, int PROF, bool ONE_CMP = false>
-__device__ __forceinline__ void drift_at(const Consts<R>& c, R x, R hh, R& ah, R& sb) {
+__device__ __forceinline__ void drift_at(const Consts<R>& c, R x, R hh, R& ah, R& bh) {
     if (PROF == KPROFILE_HOMOGENEOUS) {
         ah = (R)0;
-        sb = (R)0;
+        bh = (R)0;
     } else {
         const bool inside = ONE_CMP ? Math<R>::clamp_(x, c.eps, c.Hme) == x : (x >= c.eps) && (x <= c.Hme);
         const R d = c.H - x;
         const R q = inside ? Math<R>::rsqrt(d) : (R)0;
         ah = ((c.acoef_h * hh) * d) * q;
-        sb = Math<R>::sqrt_((R)0.75 * hh) * q;
+        bh = (((R)0.75 * hh) * q) * q;
     }
 }
 
-// U - a' - b' U^2 (a B half-step with a' = a hh, b' = b hh): b' U and U - a' are
-// independent, so two operations follow U.
+// A B half-step U - a' - b' U^2 (a' = a hh, b' = b hh) in Horner form,
+// U (1 - b' U) - a': two fused multiply-adds.
 template <typename R>
 __device__ __forceinline__ R kick(R u, R ah, R bh) {
-    return (u - ah) - (bh * u) * u;
-}
-
-// The same half-step with b' given by its square root sb (drift_at): U - a' - (sb U)^2.
-// Two BAOAB half-steps share one (ah, sb), so b' itself is never formed.
-template <typename R>
-__device__ __forceinline__ R kick_sb(R u, R ah, R sb) {
-    const R t = sb * u;
-    return (u - ah) - t * t;
+    return Math<R>::fma_(u, Math<R>::fma_(-bh, u, (R)1), -ah);
 }
 
 template <typename R>
 struct Path {
     R x, u;
     uint32_t sgn;   // reflection sign S as a sign-bit mask (0: S = +1)
-    R a, b;         // BAOAB: ah and sb of drift_at at x, carried to the next step
+    R a, b;         // BAOAB: ah and bh of drift_at at x, carried to the next step
     bool bad;       // ran away (more than kFoldMax reflections): non-finite
 };
 
@@ -409,8 +399,9 @@ __device__ __forceinline__ void step_impl(const Consts<R>& c, Path<R>& p, R h, R
         if (!COARSE) tilde = Math<R>::flip(xi, p.sgn);
         const R amp = sr * Math<R>::sqrt_((R)-2 * z);                  // sigma sqrt(h) / sxi
         const R u0 = p.u;
-        const R lin = ((R)1 + z) * u0 - ah;                          // (1 - lambda h) U - a h
-        p.u = Math<R>::fma_(amp, noise, lin - (bh * u0) * u0);       // - b h U^2 + sigma dW
+        // (1 - lambda h) U - a h - b h U^2 + sigma dW, as U ((1 - lambda h) - b h U) - a h
+        // + sigma dW
+        p.u = Math<R>::fma_(u0, Math<R>::fma_(-bh, u0, (R)1 + z), Math<R>::fma_(amp, noise, -ah));
         p.x = p.x + p.u * h;
         fold_or_track<R, FOLD>(p, c.H, key);
         w = (R)1;
@@ -429,7 +420,7 @@ __device__ __forceinline__ void step_impl(const Consts<R>& c, Path<R>& p, R h, R
         p.x = p.x + p.u * h;                                         // A
         fold_or_track<R, FOLD>(p, c.H, key);
     } else {                                                         // Eq. (10)
-        p.u = kick_sb(p.u, p.a, p.b);                                // B at (X_n, U_n)
+        p.u = kick(p.u, p.a, p.b);                                   // B at (X_n, U_n)
         p.x = p.x + p.u * hh;                                        // A
         fold_or_track<R, FOLD>(p, c.H, key);
         R sr, z;
@@ -445,7 +436,7 @@ __device__ __forceinline__ void step_impl(const Consts<R>& c, Path<R>& p, R h, R
         p.x = p.x + p.u * hh;                                        // A
         fold_or_track<R, FOLD>(p, c.H, key);
         drift_at<R, PROF, FOLD == FOLD_TRACK>(c, p.x, hh, p.a, p.b);
-        p.u = kick_sb(p.u, p.a, p.b);                                // B at (X_{n+1}, U*)
+        p.u = kick(p.u, p.a, p.b);                                   // B at (X_{n+1}, U*)
     }
 }
 
