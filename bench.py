@@ -20,6 +20,7 @@ import argparse
 import hashlib
 import json
 import os
+import statistics
 import struct
 import sys
 import time
@@ -477,9 +478,12 @@ def batched_report(ld, steps, warmup, autotune=True):
                 eng.run(queries)
             torch.cuda.synchronize()
             dev0 = eng.stats()["device_seconds"]
+            each = []   # eng.run returns with every result, so each batch is timed whole
             t0 = time.perf_counter()
             for _ in range(steps):
+                t1 = time.perf_counter()
                 out = eng.run(queries)
+                each.append(time.perf_counter() - t1)
             dt = (time.perf_counter() - t0) / steps
             dev_s = (eng.stats()["device_seconds"] - dev0) / steps
         # the one-call form, which creates and frees an engine (about 1 GiB) each time
@@ -491,6 +495,7 @@ def batched_report(ld, steps, warmup, autotune=True):
                   for r, q in zip(out, spec))
         achieved = ops / dev_s / 1e12
         res[prec] = {"seconds": dt, "coupled_steps_per_s": fs / dt, "fine_steps": fs,
+                     "median_seconds": statistics.median(each), "max_seconds": max(each),
                      "kernel_seconds": dev_s,
                      "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_TFLOPS[prec],
                                   "unit": "TFLOP/s", "frac": achieved / PEAK_TFLOPS[prec],
