@@ -268,10 +268,45 @@ __device__ __forceinline__ void pipe_coarse_chunk(const Consts<R>& c, Path<R>& p
     }
 }
 
-template <typename R, int INTEG, int PROF>
-__device__ __forceinline__ void pipe_samples(const KProblem& kp, const Consts<R>& c,
-                                             const KItem& item, uint32_t local_block, Acc& acc,
-                                             double* dump, PipeLds<R>& L) {
+// The fine wave's chunk with o_step_expm1's tier TIER, or (TIER < 0) the tier `tier`
+// chosen at run time, chunk by chunk.
+template <typename R, int INTEG, int PROF, int TIER, bool FULL>
+__device__ __forceinline__ void fine_chunk_tier(int tier, const Consts<R>& c, Path<R>& p, R h, R hh,
+                                                PipeLds<R>& L, uint32_t b3, uint32_t b2,
+                                                uint32_t m0, uint32_t P, int lane) {
+    if constexpr (TIER >= 0) {
+        pipe_fine_chunk<R, INTEG, PROF, TIER, FULL>(c, p, h, hh, L, b3, b2, m0, P, lane);
+    } else if (tier == 2) {
+        pipe_fine_chunk<R, INTEG, PROF, 2, FULL>(c, p, h, hh, L, b3, b2, m0, P, lane);
+    } else if (tier == 1) {
+        pipe_fine_chunk<R, INTEG, PROF, 1, FULL>(c, p, h, hh, L, b3, b2, m0, P, lane);
+    } else {
+        pipe_fine_chunk<R, INTEG, PROF, 0, FULL>(c, p, h, hh, L, b3, b2, m0, P, lane);
+    }
+}
+
+template <typename R, int INTEG, int PROF, int TIER>
+__device__ __forceinline__ void coarse_chunk_tier(int tier, const Consts<R>& c, Path<R>& p, R h2, R h,
+                                                  PipeLds<R>& L, uint32_t b3, uint32_t b2,
+                                                  uint32_t m0, uint32_t P, int lane) {
+    if constexpr (TIER >= 0) {
+        pipe_coarse_chunk<R, INTEG, PROF, TIER>(c, p, h2, h, L, b3, b2, m0, P, lane);
+    } else if (tier == 2) {
+        pipe_coarse_chunk<R, INTEG, PROF, 2>(c, p, h2, h, L, b3, b2, m0, P, lane);
+    } else if (tier == 1) {
+        pipe_coarse_chunk<R, INTEG, PROF, 1>(c, p, h2, h, L, b3, b2, m0, P, lane);
+    } else {
+        pipe_coarse_chunk<R, INTEG, PROF, 0>(c, p, h2, h, L, b3, b2, m0, P, lane);
+    }
+}
+
+// TF, TC: o_step_expm1's tiers of the fine and the coarse path, fixed for the block (no
+// chunk re-tests them), or -1: each chunk takes them from the path's step (see
+// pipe_samples).
+template <typename R, int INTEG, int PROF, int TF, int TC>
+__device__ __forceinline__ void pipe_samples_t(const KProblem& kp, const Consts<R>& c,
+                                               const KItem& item, uint32_t local_block, Acc& acc,
+                                               double* dump, PipeLds<R>& L) {
     constexpr int K = kPipeChunk;
     auto& nrm = L.nrm;
     auto& end_pc = L.end_pc;
@@ -285,9 +320,8 @@ __device__ __forceinline__ void pipe_samples(const KProblem& kp, const Consts<R>
     const uint32_t nch = (P + K - 1) / K;
     const double hd = kp.T / (double)M;
     const R h = (R)hd, hh = (R)(0.5 * hd), h2 = (R)(2.0 * hd);
-    // o_step_expm1's tier per path from its own step, as in run_sample
-    const int tier_f = expm1_tier<R>(kp, INTEG, hd);
-    const int tier_c = expm1_tier<R>(kp, INTEG, 2.0 * hd);
+    const int tier_f = TF >= 0 ? TF : expm1_tier<R>(kp, INTEG, hd);
+    const int tier_c = TC >= 0 ? TC : expm1_tier<R>(kp, INTEG, 2.0 * hd);
     const Stream st = make_stream(kp.seed, kp.stream_id, level, item.sample_begin + local);
     Path<R> p;
     if (wave >= 2) {
@@ -315,30 +349,15 @@ __device__ __forceinline__ void pipe_samples(const KProblem& kp, const Consts<R>
         } else if (wave == 2) {
             if (s >= 1 && s <= nch) {
                 const uint32_t b3 = r3 == 0 ? 2u : r3 - 1, b2 = (s - 1) & 1, m0 = (s - 1) * K;
-                if (m0 + K <= P) {
-                    if (tier_f == 2)
-                        pipe_fine_chunk<R, INTEG, PROF, 2, true>(c, p, h, hh, L, b3, b2, m0, P, lane);
-                    else if (tier_f == 1)
-                        pipe_fine_chunk<R, INTEG, PROF, 1, true>(c, p, h, hh, L, b3, b2, m0, P, lane);
-                    else
-                        pipe_fine_chunk<R, INTEG, PROF, 0, true>(c, p, h, hh, L, b3, b2, m0, P, lane);
-                } else if (tier_f == 2) {
-                    pipe_fine_chunk<R, INTEG, PROF, 2, false>(c, p, h, hh, L, b3, b2, m0, P, lane);
-                } else if (tier_f == 1) {
-                    pipe_fine_chunk<R, INTEG, PROF, 1, false>(c, p, h, hh, L, b3, b2, m0, P, lane);
-                } else {
-                    pipe_fine_chunk<R, INTEG, PROF, 0, false>(c, p, h, hh, L, b3, b2, m0, P, lane);
-                }
+                if (m0 + K <= P)
+                    fine_chunk_tier<R, INTEG, PROF, TF, true>(tier_f, c, p, h, hh, L, b3, b2, m0, P, lane);
+                else
+                    fine_chunk_tier<R, INTEG, PROF, TF, false>(tier_f, c, p, h, hh, L, b3, b2, m0, P, lane);
             }
         } else {
             if (s >= 2) {
                 const uint32_t b3 = r3 == 2 ? 0u : r3 + 1, b2 = s & 1, m0 = (s - 2) * K;   // (s - 2) mod 3, mod 2
-                if (tier_c == 2)
-                    pipe_coarse_chunk<R, INTEG, PROF, 2>(c, p, h2, h, L, b3, b2, m0, P, lane);
-                else if (tier_c == 1)
-                    pipe_coarse_chunk<R, INTEG, PROF, 1>(c, p, h2, h, L, b3, b2, m0, P, lane);
-                else
-                    pipe_coarse_chunk<R, INTEG, PROF, 0>(c, p, h2, h, L, b3, b2, m0, P, lane);
+                coarse_chunk_tier<R, INTEG, PROF, TC>(tier_c, c, p, h2, h, L, b3, b2, m0, P, lane);
             }
         }
         r3 = r3 == 2 ? 0u : r3 + 1;
@@ -362,6 +381,38 @@ __device__ __forceinline__ void pipe_samples(const KProblem& kp, const Consts<R>
 }
 
 // Wave priority (s_setprio takes an immediate): the longest paths of a launch first.
+// A PIPE block's samples, with o_step_expm1's tier per path from its own step (h fine, 2h
+// coarse; PIPE levels are >= 1), as in run_sample. The coarse tier never exceeds the fine
+// one, FP64 has no tier 2 and symplectic Euler none but 0. FP32 blocks fix the tiers for
+// the whole block: the fine wave's chunk is then one straight run (level 12 of the single
+// large workload 7 % faster). FP64 blocks choose them chunk by chunk: fixed tiers made FP64
+// level 12 alone 5 % faster but the estimate, whose long levels share CUs with each other
+// and with the short levels' launch, 3 % slower.
+template <typename R, int INTEG, int PROF>
+__device__ __forceinline__ void pipe_samples(const KProblem& kp, const Consts<R>& c,
+                                             const KItem& item, uint32_t local_block, Acc& acc,
+                                             double* dump, PipeLds<R>& L) {
+    if constexpr (INTEG == KINTEG_SE) {
+        pipe_samples_t<R, INTEG, PROF, 0, 0>(kp, c, item, local_block, acc, dump, L);
+    } else if constexpr (sizeof(R) == 8) {
+        pipe_samples_t<R, INTEG, PROF, -1, -1>(kp, c, item, local_block, acc, dump, L);
+    } else {
+        const double hd = kp.T / (double)((uint32_t)kp.M0 << item.level);
+        const int tf = expm1_tier<R>(kp, INTEG, hd);
+        const int tc = expm1_tier<R>(kp, INTEG, 2.0 * hd);
+        if (tc == 2)
+            pipe_samples_t<R, INTEG, PROF, 2, 2>(kp, c, item, local_block, acc, dump, L);
+        else if (tf == 2)
+            pipe_samples_t<R, INTEG, PROF, 2, 1>(kp, c, item, local_block, acc, dump, L);
+        else if (tc >= 1)
+            pipe_samples_t<R, INTEG, PROF, 1, 1>(kp, c, item, local_block, acc, dump, L);
+        else if (tf >= 1)
+            pipe_samples_t<R, INTEG, PROF, 1, 0>(kp, c, item, local_block, acc, dump, L);
+        else
+            pipe_samples_t<R, INTEG, PROF, 0, 0>(kp, c, item, local_block, acc, dump, L);
+    }
+}
+
 __device__ __forceinline__ void set_priority(uint32_t prio) {
     switch (prio) {
         case 3: __builtin_amdgcn_s_setprio(3); break;
