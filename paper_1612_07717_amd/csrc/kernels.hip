@@ -177,12 +177,32 @@ __device__ __forceinline__ void accumulate(Acc& acc, double pf, double pc, bool 
 // coarse wave forms S xi itself from the normals and the fine path's S over the chunk,
 // which the fine wave publishes once per chunk with e^{-lambda h} of every first step of
 // a pair. Normals are triple-buffered (drawn, fine, coarse), messages double-buffered;
-// one barrier per chunk of kPipeChunk coarse steps; the arithmetic per path is that of
+// one barrier per chunk of pipe_chunk<R>() coarse steps; the arithmetic per path is that of
 // STREAM mode.
+// Coarse steps per chunk: 16 for FP32 paths, whose chunks are unrolled whole (a chunk's
+// fixed cost, the saved state, the LDS addresses, the repeat test and the barrier,
+// spread over 32 fine steps; FP32 level 12 of the single large workload 7 % faster than
+// with 8), kPipeChunk = 8 for FP64 paths (twice the LDS per element, and the compiler's
+// own unrolling: forcing it spills).
+template <typename R>
+constexpr int pipe_chunk() { return sizeof(R) == 4 ? 2 * kPipeChunk : kPipeChunk; }
+
+// for (j = 0; j < pipe_chunk<R>(); ++j) body(j), unrolled whole for FP32 paths, left to the
+// compiler for FP64 ones.
+template <typename R, typename F>
+__device__ __forceinline__ void chunk_loop(F&& body) {
+    if constexpr (sizeof(R) == 4) {
+#pragma unroll
+        for (int j = 0; j < pipe_chunk<R>(); ++j) body(j);
+    } else {
+        for (int j = 0; j < pipe_chunk<R>(); ++j) body(j);
+    }
+}
+
 template <typename R>
 struct PipeLds {
-    R nrm[3][kPipeChunk][2][64];   // scaled normals of a chunk (S xi after a repeated chunk)
-    R msg[2][kPipeChunk][64];      // fine -> coarse: e^{-lambda h} of fine step 2m
+    R nrm[3][pipe_chunk<R>()][2][64];   // scaled normals of a chunk (S xi after a repeated chunk)
+    R msg[2][pipe_chunk<R>()][64];      // fine -> coarse: e^{-lambda h} of fine step 2m
     uint32_t sgn[2][64];           // fine -> coarse: the fine path's S over the chunk
     double end_pc[64];
     int end_bad[64];
@@ -204,20 +224,20 @@ __device__ __forceinline__ void pipe_fine_chunk(const Consts<R>& c, Path<R>& p, 
                                                 uint32_t m0, uint32_t P, int lane) {
     const Path<R> p0 = p;
     uint32_t key = 0;
-    for (int j = 0; j < kPipeChunk; ++j) {
+    chunk_loop<R>([&](int j) {
         if (FULL || m0 + j < P) {
             R ta, tb, wa, wb;
             step_impl<R, INTEG, PROF, false, TIER, FOLD_TRACK>(c, p, h, hh, L.nrm[b3][j][0][lane], ta, wa, key);
             step_impl<R, INTEG, PROF, false, TIER, FOLD_TRACK>(c, p, h, hh, L.nrm[b3][j][1][lane], tb, wb, key);
             if (INTEG != KINTEG_SE) L.msg[b2][j][lane] = wa;
         }
-    }
+    });
     const bool repeat = key > FoldKey<R>::limit(c.H);
     L.sgn[b2][lane] = repeat ? 0u : p0.sgn;
     if (__builtin_expect(repeat, 0)) {
         p = p0;
 #pragma unroll 1
-        for (int j = 0; j < kPipeChunk; ++j) {
+        for (int j = 0; j < pipe_chunk<R>(); ++j) {
             if (m0 + j < P) {
                 R ta, tb, wa, wb;
                 step<R, INTEG, PROF, false, TIER>(c, p, h, hh, L.nrm[b3][j][0][lane], ta, wa);
@@ -238,7 +258,7 @@ __device__ __forceinline__ void coarse_steps(const Consts<R>& c, Path<R>& p, R h
                                              PipeLds<R>& L, uint32_t b3, uint32_t b2,
                                              uint32_t m0, uint32_t P, int lane, uint32_t& key) {
     const uint32_t sf = L.sgn[b2][lane];
-    for (int j = 0; j < kPipeChunk; ++j) {
+    chunk_loop<R>([&](int j) {
         if (m0 + j < P) {
             const R ta = Math<R>::flip(L.nrm[b3][j][0][lane], sf);
             const R tb = Math<R>::flip(L.nrm[b3][j][1][lane], sf);
@@ -252,7 +272,7 @@ __device__ __forceinline__ void coarse_steps(const Consts<R>& c, Path<R>& p, R h
             R unused_t, unused_w;
             step_impl<R, INTEG, PROF, true, TIER, FOLD>(c, p, h2, h, xi_c, unused_t, unused_w, key);
         }
-    }
+    });
 }
 
 template <typename R, int INTEG, int PROF, int TIER>
@@ -307,7 +327,7 @@ template <typename R, int INTEG, int PROF, int TF, int TC>
 __device__ __forceinline__ void pipe_samples_t(const KProblem& kp, const Consts<R>& c,
                                                const KItem& item, uint32_t local_block, Acc& acc,
                                                double* dump, PipeLds<R>& L) {
-    constexpr int K = kPipeChunk;
+    constexpr int K = pipe_chunk<R>();
     auto& nrm = L.nrm;
     auto& end_pc = L.end_pc;
     auto& end_bad = L.end_bad;
