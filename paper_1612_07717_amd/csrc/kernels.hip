@@ -644,8 +644,19 @@ __global__ __launch_bounds__(kBlock, 3) void level_kernel(const KArgs args,
     set_priority(item.prio);
     Acc acc;
     acc_zero(acc);
-    __shared__ PipeLds<R> lds;
-    run_block<R, INTEG, PROF>(args.prob, item, b - item.block_begin, acc, dump, lds);
+    // the PIPE blocks' hand-off area. FP32: dynamic, a launch brings sizeof(PipeLds<float>)
+    // bytes only if one of its items runs PIPE blocks (launch_levels), so that STREAM-only
+    // launches keep the occupancy their registers allow (6 blocks per CU rather than the 4
+    // that 34 KB allow). FP64: static (its blocks fit 3 per CU by registers anyway; the
+    // dynamic form made the FP64 estimate 3 % slower)
+    if constexpr (sizeof(R) == 4) {
+        extern __shared__ __align__(16) unsigned char pipe_lds[];
+        run_block<R, INTEG, PROF>(args.prob, item, b - item.block_begin, acc, dump,
+                                  *reinterpret_cast<PipeLds<R>*>(pipe_lds));
+    } else {
+        __shared__ PipeLds<R> lds;
+        run_block<R, INTEG, PROF>(args.prob, item, b - item.block_begin, acc, dump, lds);
+    }
     block_reduce(acc);
     if (threadIdx.x == 0) store_sums(&partials[b], acc);
 }
@@ -1025,7 +1036,10 @@ int launch_levels(const KArgs& args, uint32_t total_blocks, ld_level_sums* d_par
         const LevelKernel k = (args.precision == LD_FP32)
                                   ? pick_kernel<float>(args.prob.integ, args.prob.profile, args.prob.adaptive, wide)
                                   : pick_kernel<double>(args.prob.integ, args.prob.profile, args.prob.adaptive, wide);
-        hipLaunchKernelGGL(k, dim3(total_blocks), dim3(kBlock), 0, s, args, d_partials, d_dump);
+        bool pipe = false;
+        for (int i = 0; i < args.n_items; ++i) pipe |= args.items[i].mode == KMODE_PIPE;
+        const size_t lds = (pipe && args.precision == LD_FP32) ? sizeof(PipeLds<float>) : 0;
+        hipLaunchKernelGGL(k, dim3(total_blocks), dim3(kBlock), lds, s, args, d_partials, d_dump);
         if (hipGetLastError() != hipSuccess) return LD_EDEVICE;
     }
     hipLaunchKernelGGL(merge_kernel, dim3(args.n_items), dim3(kBlock), 0, s, args, d_partials, d_out);
