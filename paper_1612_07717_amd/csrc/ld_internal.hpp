@@ -26,7 +26,7 @@ constexpr int kMaxCoef = 10;      // smoothing polynomial p_r, r <= 8
 // the fine paths, one the coarse paths - handing data through LDS, so the per-sample
 // instruction stream of the critical (fine) wave is short (latency of long paths).
 enum { KMODE_STREAM = 0, KMODE_PIPE = 1 };
-constexpr int kPipeChunk = 8;                     // coarse steps per LDS hand-off
+constexpr int kPipeChunk = 8;                     // coarse steps per LDS hand-off (FP64; FP32 twice that)
 constexpr uint64_t kPipeMaxSamples = 64u * 2048u; // larger ranges fill the GPU in STREAM mode
 constexpr uint32_t kPipeMinSteps = 256;           // shorter paths are not latency-critical
 
