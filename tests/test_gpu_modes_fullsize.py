@@ -81,6 +81,28 @@ def test_pipe_and_stream_agree_on_the_short_series_boundary_level(integ, prec, M
         assert np.all(np.abs(pipe[:48] - ref) <= tol)
 
 
+# PIPE blocks advance their paths in chunks of 16 coarse steps (FP32 paths) or 8 (FP64);
+# a path's last chunk is cut short where P = M_l / 2 is not a multiple of that. With
+# M_0 = 41, level 3 has P = 164 (ragged in both precisions), level 4 P = 328 (FP32 only).
+RAGGED = [("BAOAB", "fp32", 3), ("GL", "fp32", 3), ("SE", "fp32", 3), ("BAOAB", "fp32", 4),
+          ("BAOAB", "fp64", 3), ("GL", "fp64", 3)]
+
+
+@pytest.mark.parametrize("integ,prec,level", RAGGED)
+def test_pipe_ragged_last_chunk_agrees_with_stream(integ, prec, level):
+    cfg = W.neutral(500.0, integ, M0=41)
+    P = (41 << level) // 2
+    assert P % (16 if prec == "fp32" else 8) != 0
+    say(f"case ragged {integ} {prec} level={level}")
+    pipe = ld.level_samples(cfg, level, 7, PIPE_MAX, prec)        # PIPE blocks
+    stream = ld.level_samples(cfg, level, 7, PIPE_MAX + 1, prec)  # STREAM blocks
+    assert np.array_equal(pipe, stream[:PIPE_MAX])
+    if prec == "fp64":
+        ref = oracle.level_samples(cfg, level, 7, 48)
+        tol = 1e-12 * np.maximum(np.abs(ref), 1e-3 * cfg["H"])
+        assert np.all(np.abs(pipe[:48] - ref) <= tol)
+
+
 @pytest.mark.parametrize("H", [100.0, 400.0])
 @pytest.mark.parametrize("integ,prec", [("BAOAB", "fp32"), ("SE", "fp64"), ("GL", "fp64"), ("BAOAB", "fp64")])
 def test_pipe_and_stream_agree_when_steps_cross_the_layer(integ, prec, H):
